@@ -1,0 +1,523 @@
+/*
+ * FastFCA reference oracle -- plain, slow, double precision, CPU only.
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the package smoke check and the
+ * CPU-baseline leg of the benchmark may load this library. The GPU library
+ * shares no code, header, table or helper with this file.
+ *
+ * Source: Ito, Ikeshita, Sawada, Nakatani, "A Joint Diagonalization Based
+ * Efficient Approach to Underdetermined Blind Audio Source Separation Using
+ * the Multichannel Wiener Filter" (arXiv 2101.08563).
+ *
+ * Notation (paper -> here): frequency i -> f, frame j -> t, decorrelation
+ * matrix W -> P (columns w_m = P[:,m]), [L]_{mn} = [Lambda_n]_{mm} -> lam[n][m],
+ * [H]_{nj} = h_{jn} -> v[t][n], sigma^2_{mj} = [LH]_{mj} -> sigma2(m,t),
+ * [U]_{mj} = |w_m^H x_j|^2 -> U[m][t].
+ *
+ * Every frequency is an independent problem (Sec. II; Sec. IV-G), so all
+ * per-frequency routines take one frequency's arrays.
+ *
+ * Layouts (row-major, C order):
+ *   x   [T][M]    complex   mixture STFT of one frequency
+ *   P   [M][M]    complex   P[r][c]; column c is w_c
+ *   lam [N][M]    real > 0
+ *   v   [T][N]    real > 0
+ *   U   [M][T]    real >= 0
+ *   Q   [M][M][M] complex   Q[m][r][c] = [Q_m]_{rc}
+ *
+ * Floating point: IEEE double throughout; built without fast-math.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+#define OFC_OK 0
+#define OFC_E_ARG (-1)
+#define OFC_E_NOMEM (-2)
+#define OFC_E_SINGULAR (-4)
+
+/* Relative pivot threshold below which a linear solve is declared singular. */
+#define OFC_PIVOT_TOL 1e-12
+
+/* sigma^2_{mt} = sum_n h_{tn} [Lambda_n]_{mm}  (Sec. IV-D, eq:sigmadef). */
+static double sigma2_at(int M, int N, const double *lam, const double *vt, int m)
+{
+    double s = 0.0;
+    for (int n = 0; n < N; ++n)
+        s += vt[n] * lam[n * M + m];
+    return s;
+}
+
+/*
+ * Weighted covariances, all m at once (Sec. IV-E, eq:wsampcov; Algorithm 1,
+ * first step of the loop over m). Q_m depends only on L and H, so computing
+ * all of them before the IP sweep gives the same matrices.
+ *   Q_m = (1/T) sum_t x_t x_t^H / sigma^2_{mt}
+ */
+void ofc_weighted_cov(int T, int M, int N, const cplx *x, const double *lam,
+                      const double *v, cplx *Q)
+{
+    memset(Q, 0, sizeof(cplx) * (size_t)M * M * M);
+    for (int t = 0; t < T; ++t) {
+        const cplx *xt = x + (size_t)t * M;
+        const double *vt = v + (size_t)t * N;
+        for (int m = 0; m < M; ++m) {
+            double w = 1.0 / sigma2_at(M, N, lam, vt, m);
+            cplx *Qm = Q + (size_t)m * M * M;
+            for (int r = 0; r < M; ++r)
+                for (int c = 0; c < M; ++c)
+                    Qm[r * M + c] += w * xt[r] * conj(xt[c]);
+        }
+    }
+    for (int i = 0; i < M * M * M; ++i)
+        Q[i] /= (double)T;
+}
+
+/*
+ * Solve A z = b in place (A is n x n, row-major) by Gaussian elimination with
+ * partial pivoting. A and b are overwritten; the solution is left in b.
+ * Returns OFC_E_SINGULAR when a pivot is tiny relative to the largest entry.
+ */
+static int lu_solve(int n, cplx *A, cplx *b)
+{
+    double amax = 0.0;
+    for (int i = 0; i < n * n; ++i)
+        if (cabs(A[i]) > amax)
+            amax = cabs(A[i]);
+    if (!(amax > 0.0) || !isfinite(amax))
+        return OFC_E_SINGULAR;
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        double best = cabs(A[k * n + k]);
+        for (int i = k + 1; i < n; ++i) {
+            double a = cabs(A[i * n + k]);
+            if (a > best) {
+                best = a;
+                p = i;
+            }
+        }
+        if (best < OFC_PIVOT_TOL * amax)
+            return OFC_E_SINGULAR;
+        if (p != k) {
+            for (int j = 0; j < n; ++j) {
+                cplx tmp = A[k * n + j];
+                A[k * n + j] = A[p * n + j];
+                A[p * n + j] = tmp;
+            }
+            cplx tmp = b[k];
+            b[k] = b[p];
+            b[p] = tmp;
+        }
+        for (int i = k + 1; i < n; ++i) {
+            cplx l = A[i * n + k] / A[k * n + k];
+            for (int j = k; j < n; ++j)
+                A[i * n + j] -= l * A[k * n + j];
+            b[i] -= l * b[k];
+        }
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        cplx s = b[i];
+        for (int j = i + 1; j < n; ++j)
+            s -= A[i * n + j] * b[j];
+        b[i] = s / A[i * n + i];
+    }
+    return OFC_OK;
+}
+
+/*
+ * One IP column update (Sec. IV-E, eq:ip1 then eq:ip2):
+ *   w_m <- (P^H Q_m)^{-1} e_m ;  w_m <- w_m / sqrt(w_m^H Q_m w_m)
+ * P is updated in place (column m replaced).
+ */
+int ofc_ip_column(int M, cplx *P, const cplx *Qm, int m)
+{
+    if (M < 1 || M > 64 || m < 0 || m >= M)
+        return OFC_E_ARG;
+    cplx A[64 * 64];
+    cplx w[64];
+    /* A = P^H Q_m */
+    for (int r = 0; r < M; ++r)
+        for (int c = 0; c < M; ++c) {
+            cplx s = 0.0;
+            for (int k = 0; k < M; ++k)
+                s += conj(P[k * M + r]) * Qm[k * M + c];
+            A[r * M + c] = s;
+        }
+    for (int r = 0; r < M; ++r)
+        w[r] = (r == m) ? 1.0 : 0.0;
+    int st = lu_solve(M, A, w);
+    if (st != OFC_OK)
+        return st;
+    /* w^H Q_m w is real and positive for Hermitian PD Q_m. */
+    cplx q = 0.0;
+    for (int r = 0; r < M; ++r) {
+        cplx s = 0.0;
+        for (int c = 0; c < M; ++c)
+            s += Qm[r * M + c] * w[c];
+        q += conj(w[r]) * s;
+    }
+    double qr = creal(q);
+    if (!(qr > 0.0) || !isfinite(qr))
+        return OFC_E_SINGULAR;
+    double inv = 1.0 / sqrt(qr);
+    for (int r = 0; r < M; ++r)
+        P[r * M + m] = w[r] * inv;
+    return OFC_OK;
+}
+
+/* U_{mt} = |w_m^H x_t|^2  (Sec. IV-E, eq:Udef; Algorithm 1 update of U). */
+void ofc_decorrelated_power(int T, int M, const cplx *P, const cplx *x, double *U)
+{
+    for (int t = 0; t < T; ++t) {
+        const cplx *xt = x + (size_t)t * M;
+        for (int m = 0; m < M; ++m) {
+            cplx y = 0.0;
+            for (int r = 0; r < M; ++r)
+                y += conj(P[r * M + m]) * xt[r];
+            U[(size_t)m * T + t] = creal(y) * creal(y) + cimag(y) * cimag(y);
+        }
+    }
+}
+
+/*
+ * EM update of source n for the channel-time IS-NMF U ~ LH (Algorithm 1, the
+ * body of the loop over n): posterior gain G_n and posterior power Phi_n from
+ * the current L and H, then column n of L from Phi_n and the old row n of H,
+ * then row n of H from Phi_n and the new column n of L.
+ * phi is scratch of M*T doubles.
+ */
+void ofc_em_source(int T, int M, int N, const double *U, double *lam, double *v,
+                   int n, double *phi)
+{
+    for (int t = 0; t < T; ++t) {
+        const double *vt = v + (size_t)t * N;
+        for (int m = 0; m < M; ++m) {
+            double s2 = sigma2_at(M, N, lam, vt, m);
+            double a = vt[n] * lam[n * M + m];
+            double g = a / s2;
+            phi[(size_t)m * T + t] = g * g * U[(size_t)m * T + t] + (1.0 - g) * a;
+        }
+    }
+    for (int m = 0; m < M; ++m) {
+        double s = 0.0;
+        for (int t = 0; t < T; ++t)
+            s += phi[(size_t)m * T + t] / v[(size_t)t * N + n];
+        lam[n * M + m] = s / (double)T;
+    }
+    for (int t = 0; t < T; ++t) {
+        double s = 0.0;
+        for (int m = 0; m < M; ++m)
+            s += phi[(size_t)m * T + t] / lam[n * M + m];
+        v[(size_t)t * N + n] = s / (double)M;
+    }
+}
+
+/*
+ * MM update of L then H, all sources at once (Algorithm 2, the two
+ * multiplicative square-root rules). scratch holds 2*M*T doubles.
+ */
+void ofc_mm_update(int T, int M, int N, const double *U, double *lam, double *v,
+                   double *scratch)
+{
+    double *a = scratch;                 /* U / (LH)^2  [M][T] */
+    double *b = scratch + (size_t)M * T; /* 1 / (LH)    [M][T] */
+    for (int t = 0; t < T; ++t)
+        for (int m = 0; m < M; ++m) {
+            double s2 = sigma2_at(M, N, lam, v + (size_t)t * N, m);
+            a[(size_t)m * T + t] = U[(size_t)m * T + t] / (s2 * s2);
+            b[(size_t)m * T + t] = 1.0 / s2;
+        }
+    /* L <- L .* sqrt( (A H^T) ./ (B H^T) ) */
+    for (int m = 0; m < M; ++m)
+        for (int n = 0; n < N; ++n) {
+            double num = 0.0, den = 0.0;
+            for (int t = 0; t < T; ++t) {
+                num += a[(size_t)m * T + t] * v[(size_t)t * N + n];
+                den += b[(size_t)m * T + t] * v[(size_t)t * N + n];
+            }
+            lam[n * M + m] *= sqrt(num / den);
+        }
+    /* H is updated from the new L. */
+    for (int t = 0; t < T; ++t)
+        for (int m = 0; m < M; ++m) {
+            double s2 = sigma2_at(M, N, lam, v + (size_t)t * N, m);
+            a[(size_t)m * T + t] = U[(size_t)m * T + t] / (s2 * s2);
+            b[(size_t)m * T + t] = 1.0 / s2;
+        }
+    for (int t = 0; t < T; ++t)
+        for (int n = 0; n < N; ++n) {
+            double num = 0.0, den = 0.0;
+            for (int m = 0; m < M; ++m) {
+                num += lam[n * M + m] * a[(size_t)m * T + t];
+                den += lam[n * M + m] * b[(size_t)m * T + t];
+            }
+            v[(size_t)t * N + n] *= sqrt(num / den);
+        }
+}
+
+/* ln |det P|^2 by LU with partial pivoting. Returns -INFINITY if singular. */
+double ofc_logabsdet2(int M, const cplx *P)
+{
+    cplx A[64 * 64];
+    if (M < 1 || M > 64)
+        return NAN;
+    memcpy(A, P, sizeof(cplx) * (size_t)M * M);
+    double acc = 0.0;
+    for (int k = 0; k < M; ++k) {
+        int p = k;
+        double best = cabs(A[k * M + k]);
+        for (int i = k + 1; i < M; ++i)
+            if (cabs(A[i * M + k]) > best) {
+                best = cabs(A[i * M + k]);
+                p = i;
+            }
+        if (best == 0.0)
+            return -INFINITY;
+        if (p != k)
+            for (int j = 0; j < M; ++j) {
+                cplx tmp = A[k * M + j];
+                A[k * M + j] = A[p * M + j];
+                A[p * M + j] = tmp;
+            }
+        for (int i = k + 1; i < M; ++i) {
+            cplx l = A[i * M + k] / A[k * M + k];
+            for (int j = k; j < M; ++j)
+                A[i * M + j] -= l * A[k * M + j];
+        }
+        acc += 2.0 * log(cabs(A[k * M + k]));
+    }
+    return acc;
+}
+
+/*
+ * Per-frequency log-likelihood per TF bin, i.e. minus the negative
+ * log-likelihood of Sec. IV-D (eq:negll) divided by T, with the constant
+ * M ln(pi) per bin that eq:negll drops restored from the proper complex
+ * Gaussian density of Sec. III-A:
+ *   LL_f = ln|det P|^2 - (1/T) sum_{m,t} [ ln pi + ln sigma^2_{mt} + U_{mt}/sigma^2_{mt} ]
+ */
+double ofc_loglik_freq(int T, int M, int N, const cplx *x, const cplx *P,
+                       const double *lam, const double *v)
+{
+    const double lnpi = log(3.14159265358979323846);
+    double acc = 0.0;
+    for (int t = 0; t < T; ++t) {
+        const cplx *xt = x + (size_t)t * M;
+        const double *vt = v + (size_t)t * N;
+        for (int m = 0; m < M; ++m) {
+            cplx y = 0.0;
+            for (int r = 0; r < M; ++r)
+                y += conj(P[r * M + m]) * xt[r];
+            double u = creal(y) * creal(y) + cimag(y) * cimag(y);
+            double s2 = sigma2_at(M, N, lam, vt, m);
+            acc += lnpi + log(s2) + u / s2;
+        }
+    }
+    return ofc_logabsdet2(M, P) - acc / (double)T;
+}
+
+/*
+ * One iteration on one frequency. what: bit 0 = IP sweep over m = 1..M
+ * (ascending, each solve seeing the columns already updated), bit 1 = update
+ * of L and H. algo: 0 = EM (Algorithm 1, sources n = 1..N in order),
+ * 1 = MM (Algorithm 2). U is always recomputed from the current P before the
+ * L/H update. Qwork: M*M*M complex; dwork: 3*M*T doubles.
+ */
+int ofc_iterate_freq(int T, int M, int N, const cplx *x, cplx *P, double *lam,
+                     double *v, int what, int algo, cplx *Qwork, double *dwork)
+{
+    if (what & 1) {
+        ofc_weighted_cov(T, M, N, x, lam, v, Qwork);
+        for (int m = 0; m < M; ++m) {
+            int st = ofc_ip_column(M, P, Qwork + (size_t)m * M * M, m);
+            if (st != OFC_OK)
+                return st;
+        }
+    }
+    if (what & 2) {
+        double *U = dwork;
+        double *scratch = dwork + (size_t)M * T;
+        ofc_decorrelated_power(T, M, P, x, U);
+        if (algo == 0) {
+            for (int n = 0; n < N; ++n)
+                ofc_em_source(T, M, N, U, lam, v, n, scratch);
+        } else {
+            ofc_mm_update(T, M, N, U, lam, v, scratch);
+        }
+    }
+    return OFC_OK;
+}
+
+/*
+ * Fit all F frequencies for n_iter iterations (IP then L/H update per
+ * iteration). x [F][T][M], P [F][M][M], lam [F][N][M], v [F][T][N] updated in
+ * place. ll_trace, if non-NULL, is [F][n_iter]: per-frequency LL after each
+ * iteration. nthreads <= 0 means the OpenMP default. Returns the first error
+ * status met (frequency order), OFC_OK otherwise.
+ */
+int ofc_fit(int F, int T, int M, int N, const cplx *x, cplx *P, double *lam,
+            double *v, int n_iter, int algo, double *ll_trace, int nthreads)
+{
+    if (F < 1 || T < 1 || M < 1 || M > 64 || N < 1 || n_iter < 0)
+        return OFC_E_ARG;
+    int status = OFC_OK;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        cplx *Qw = (cplx *)malloc(sizeof(cplx) * (size_t)M * M * M);
+        double *dw = (double *)malloc(sizeof(double) * 3 * (size_t)M * T);
+#pragma omp for schedule(dynamic, 1)
+        for (int f = 0; f < F; ++f) {
+            if (!Qw || !dw) {
+#pragma omp critical
+                status = OFC_E_NOMEM;
+                continue;
+            }
+            const cplx *xf = x + (size_t)f * T * M;
+            cplx *Pf = P + (size_t)f * M * M;
+            double *lf = lam + (size_t)f * N * M;
+            double *vf = v + (size_t)f * T * N;
+            for (int it = 0; it < n_iter; ++it) {
+                int st = ofc_iterate_freq(T, M, N, xf, Pf, lf, vf, 3, algo, Qw, dw);
+                if (st != OFC_OK) {
+#pragma omp critical
+                    if (status == OFC_OK)
+                        status = st;
+                    break;
+                }
+                if (ll_trace)
+                    ll_trace[(size_t)f * n_iter + it] = ofc_loglik_freq(T, M, N, xf, Pf, lf, vf);
+            }
+        }
+        free(Qw);
+        free(dw);
+    }
+    return status;
+}
+
+/* Per-frequency LL for all F (see ofc_loglik_freq); returns the mean over f. */
+double ofc_loglik(int F, int T, int M, int N, const cplx *x, const cplx *P,
+                  const double *lam, const double *v, double *ll_f)
+{
+    double acc = 0.0;
+    for (int f = 0; f < F; ++f) {
+        double l = ofc_loglik_freq(T, M, N, x + (size_t)f * T * M, P + (size_t)f * M * M,
+                                   lam + (size_t)f * N * M, v + (size_t)f * T * N);
+        if (ll_f)
+            ll_f[f] = l;
+        acc += l;
+    }
+    return acc / (double)F;
+}
+
+/* Inverse of an M x M complex matrix by Gauss-Jordan with partial pivoting. */
+static int invert(int M, const cplx *A_in, cplx *Ainv)
+{
+    cplx A[64 * 64];
+    memcpy(A, A_in, sizeof(cplx) * (size_t)M * M);
+    for (int i = 0; i < M * M; ++i)
+        Ainv[i] = 0.0;
+    for (int i = 0; i < M; ++i)
+        Ainv[i * M + i] = 1.0;
+    for (int k = 0; k < M; ++k) {
+        int p = k;
+        double best = cabs(A[k * M + k]);
+        for (int i = k + 1; i < M; ++i)
+            if (cabs(A[i * M + k]) > best) {
+                best = cabs(A[i * M + k]);
+                p = i;
+            }
+        if (best == 0.0)
+            return OFC_E_SINGULAR;
+        if (p != k)
+            for (int j = 0; j < M; ++j) {
+                cplx t1 = A[k * M + j];
+                A[k * M + j] = A[p * M + j];
+                A[p * M + j] = t1;
+                cplx t2 = Ainv[k * M + j];
+                Ainv[k * M + j] = Ainv[p * M + j];
+                Ainv[p * M + j] = t2;
+            }
+        cplx d = A[k * M + k];
+        for (int j = 0; j < M; ++j) {
+            A[k * M + j] /= d;
+            Ainv[k * M + j] /= d;
+        }
+        for (int i = 0; i < M; ++i) {
+            if (i == k)
+                continue;
+            cplx l = A[i * M + k];
+            for (int j = 0; j < M; ++j) {
+                A[i * M + j] -= l * A[k * M + j];
+                Ainv[i * M + j] -= l * Ainv[k * M + j];
+            }
+        }
+    }
+    return OFC_OK;
+}
+
+/*
+ * Multichannel Wiener filter in the FastFCA form (Sec. IV-F, eq:Doclo):
+ *   y_{n,t} = P^{-H} diag_m( h_{tn} lam_{nm} / sigma^2_{mt} ) P^H x_t
+ * y is [N][F][T][M].
+ */
+int ofc_mwf(int F, int T, int M, int N, const cplx *x, const cplx *P,
+            const double *lam, const double *v, cplx *y)
+{
+    if (M < 1 || M > 64)
+        return OFC_E_ARG;
+    for (int f = 0; f < F; ++f) {
+        const cplx *Pf = P + (size_t)f * M * M;
+        const double *lf = lam + (size_t)f * N * M;
+        cplx Pinv[64 * 64];
+        if (invert(M, Pf, Pinv) != OFC_OK)
+            return OFC_E_SINGULAR;
+        /* B = P^{-H}: B[r][c] = conj(Pinv[c][r]) */
+        for (int t = 0; t < T; ++t) {
+            const cplx *xt = x + ((size_t)f * T + t) * M;
+            const double *vt = v + ((size_t)f * T + t) * N;
+            cplx z[64];
+            for (int m = 0; m < M; ++m) {
+                cplx s = 0.0;
+                for (int r = 0; r < M; ++r)
+                    s += conj(Pf[r * M + m]) * xt[r];
+                z[m] = s;
+            }
+            for (int n = 0; n < N; ++n) {
+                cplx *yn = y + (((size_t)n * F + f) * T + t) * M;
+                cplx gz[64];
+                for (int m = 0; m < M; ++m) {
+                    double s2 = sigma2_at(M, N, lf, vt, m);
+                    gz[m] = (vt[n] * lf[n * M + m] / s2) * z[m];
+                }
+                for (int r = 0; r < M; ++r) {
+                    cplx s = 0.0;
+                    for (int c = 0; c < M; ++c)
+                        s += conj(Pinv[c * M + r]) * gz[c];
+                    yn[r] = s;
+                }
+            }
+        }
+    }
+    return OFC_OK;
+}
+
+int ofc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
