@@ -1,0 +1,385 @@
+// Auxiliary FastFCA kernels: double precision log-likelihood, P^{-H} and
+// ln|det P|^2 per frequency, the decomposed multichannel Wiener filter, and
+// initialization / validation helpers.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace ffca {
+
+constexpr double kLnPiD = 1.1447298858494002;  // ln(pi)
+constexpr int kAuxThreads = 256;
+#define FFCA_MAXN_AUX 16
+
+// ------------------------------------------------------------------ block Gauss-Jordan
+// Invert the M x M complex matrix held in A[:, 0:M] of the LDS array
+// A[M][2M] (columns M..2M-1 must hold the identity on entry) by Gauss-Jordan
+// elimination with partial pivoting, in double precision, using every thread
+// of the block (uniform control flow). On return A[:, M:2M] holds the
+// inverse. Returns false (uniformly) if a pivot is below tol * max|A|;
+// *ldet receives ln|det A|^2.
+template <int M>
+__device__ bool block_gauss_jordan(double2 (*A)[2 * M], double &ldet, double tol) {
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    __shared__ double2 colk[M];
+    double amax2 = 0.0;
+    for (int i = 0; i < M * M; ++i) amax2 = fmax(amax2, abs2(ld(A[i / M][i % M])));
+    bool ok = (amax2 > 0.0) && (amax2 < INFINITY);
+    ldet = 0.0;
+    for (int k = 0; k < M && ok; ++k) {
+        int p = k;
+        double best = abs2(ld(A[k][k]));
+        for (int i = k + 1; i < M; ++i) {
+            const double a = abs2(ld(A[i][k]));
+            if (a > best) {
+                best = a;
+                p = i;
+            }
+        }
+        if (!(best >= tol * tol * amax2)) {
+            ok = false;
+            break;
+        }
+        ldet += log(best);
+        __syncthreads();
+        if (p != k && tid < 2 * M) {
+            const double2 t = A[k][tid];
+            A[k][tid] = A[p][tid];
+            A[p][tid] = t;
+        }
+        __syncthreads();
+        const cd piv = ld(A[k][k]);
+        __syncthreads();
+        if (tid < 2 * M) A[k][tid] = st(cdiv(ld(A[k][tid]), piv));
+        // snapshot column k (the elimination factors) before any row changes
+        if (tid < M) colk[tid] = A[tid][k];
+        __syncthreads();
+        for (int idx = tid; idx < M * 2 * M; idx += nthr) {
+            const int i = idx / (2 * M), j = idx % (2 * M);
+            if (i != k) A[i][j] = st(ld(A[i][j]) - ld(colk[i]) * ld(A[k][j]));
+        }
+        __syncthreads();
+    }
+    return ok;
+}
+
+// One workgroup per frequency: B = P^{-H} (single precision) and ln|det P|^2.
+template <int M>
+__global__ void __launch_bounds__(kAuxThreads) pinv_kernel(const WorkItem *items, float2 *Bh,
+                                                           double *ldet_out) {
+    __shared__ double2 A[M][2 * M];
+    const WorkItem &it = items[blockIdx.x];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < M * 2 * M; i += blockDim.x) {
+        const int r = i / (2 * M), c = i % (2 * M);
+        A[r][c] = c < M ? it.P[r * M + c] : make_double2(c - M == r ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    double ldet;
+    const bool ok = block_gauss_jordan<M>(A, ldet, kPivotTol);
+    if (!ok) {
+        if (tid == 0) *it.status = ST_SINGULAR;
+        if (ldet_out && tid == 0) ldet_out[blockIdx.x] = NAN;
+        return;
+    }
+    // B[r][c] = conj(Pinv[c][r])
+    if (Bh) {
+        for (int i = tid; i < M * M; i += blockDim.x) {
+            const int r = i / M, c = i % M;
+            const double2 v = A[c][M + r];
+            Bh[static_cast<size_t>(blockIdx.x) * M * M + i] =
+                make_float2(static_cast<float>(v.x), static_cast<float>(-v.y));
+        }
+    }
+    if (ldet_out && tid == 0) ldet_out[blockIdx.x] = ldet;
+}
+
+// ------------------------------------------------------------------ log-likelihood
+// LL_f = ln|det P|^2 - (1/T) sum_{m,t} [ln pi + ln sigma^2 + U / sigma^2]
+// (eq:negll with the density constant), every term in double precision.
+template <int M>
+__global__ void __launch_bounds__(kAuxThreads) loglik_kernel(const WorkItem *items,
+                                                             const double *ldet, double *ll_f) {
+    __shared__ double2 Ps[M * M];
+    __shared__ double lam_s[FFCA_MAXN_AUX * M];
+    __shared__ double red[kAuxThreads / 64];
+    const WorkItem &it = items[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int T = it.T, N = it.N;
+    if (tid < M * M) Ps[tid] = it.P[tid];
+    for (int i = tid; i < N * M; i += blockDim.x) lam_s[i] = static_cast<double>(it.lam[i]);
+    __syncthreads();
+    double acc = 0.0;
+    for (int t = tid; t < T; t += blockDim.x) {
+        double xr[M], xi[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            const float2 v = it.x[static_cast<size_t>(t) * M + r];
+            xr[r] = v.x;
+            xi[r] = v.y;
+        }
+        const float *vt = it.v + static_cast<size_t>(t) * N;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            double yr = 0.0, yi = 0.0;
+#pragma unroll
+            for (int r = 0; r < M; ++r) {
+                const double2 p = Ps[r * M + m];
+                yr += p.x * xr[r] + p.y * xi[r];
+                yi += p.x * xi[r] - p.y * xr[r];
+            }
+            const double u = yr * yr + yi * yi;
+            double s2 = 0.0;
+            for (int n = 0; n < N; ++n) s2 += static_cast<double>(vt[n]) * lam_s[n * M + m];
+            acc += kLnPiD + log(s2) + u / s2;
+        }
+    }
+    acc = wave_sum(acc);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double s = 0.0;
+        for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) s += red[w];
+        ll_f[blockIdx.x] = ldet[blockIdx.x] - s / static_cast<double>(T);
+    }
+}
+
+// ------------------------------------------------------------------ MWF (eq:Doclo)
+// Grid (ceil(T / blockDim), F). One thread per TF bin:
+//   z = P^H x ;  for each n: y_n = B (g_n .* z),  g_nm = h_n lam_nm / sigma^2_m,
+// with B = P^{-H} from pinv_kernel.
+template <int M>
+__global__ void __launch_bounds__(kAuxThreads) mwf_kernel(const WorkItem *items,
+                                                          const float2 *Bh, int F, float2 *y) {
+    __shared__ float2 Ps[M * M];
+    __shared__ float2 Bs[M * M];
+    __shared__ float lam_s[FFCA_MAXN_AUX * M];
+    const int f = blockIdx.y;
+    const WorkItem &it = items[f];
+    const int tid = threadIdx.x;
+    const int T = it.T, N = it.N;
+    if (tid < M * M) {
+        const double2 p = it.P[tid];
+        Ps[tid] = make_float2(static_cast<float>(p.x), static_cast<float>(p.y));
+        Bs[tid] = Bh[static_cast<size_t>(f) * M * M + tid];
+    }
+    for (int i = tid; i < N * M; i += blockDim.x) lam_s[i] = it.lam[i];
+    __syncthreads();
+    const int t = blockIdx.x * blockDim.x + tid;
+    if (t >= T) return;
+    float2 x[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) x[r] = it.x[static_cast<size_t>(t) * M + r];
+    float2 z[M];
+    float rs[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        float zr = 0.f, zi = 0.f;
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            const float2 p = Ps[r * M + m];
+            zr = fmaf(p.x, x[r].x, fmaf(p.y, x[r].y, zr));
+            zi = fmaf(p.x, x[r].y, fmaf(-p.y, x[r].x, zi));
+        }
+        z[m] = make_float2(zr, zi);
+    }
+    const float *vt = it.v + static_cast<size_t>(t) * N;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        float s = 0.f;
+        for (int n = 0; n < N; ++n) s = fmaf(vt[n], lam_s[n * M + m], s);
+        rs[m] = rcp(s);
+    }
+    for (int n = 0; n < N; ++n) {
+        const float vn = vt[n];
+        float2 gz[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const float g = vn * lam_s[n * M + m] * rs[m];
+            gz[m] = make_float2(g * z[m].x, g * z[m].y);
+        }
+        float2 *yo = y + ((static_cast<size_t>(n) * F + f) * T + t) * M;
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            float ar = 0.f, ai = 0.f;
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const float2 b = Bs[r * M + c];
+                ar = fmaf(b.x, gz[c].x, fmaf(-b.y, gz[c].y, ar));
+                ai = fmaf(b.x, gz[c].y, fmaf(b.y, gz[c].x, ai));
+            }
+            yo[r] = make_float2(ar, ai);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ helpers
+__global__ void check_finite_x_kernel(const float2 *x, size_t n, int *flag) {
+    bool bad = false;
+    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const float2 v = x[i];
+        bad = bad || !(fabsf(v.x) < INFINITY) || !(fabsf(v.y) < INFINITY);
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+__global__ void check_positive_kernel(const float *a, size_t n, int *flag) {
+    bool bad = false;
+    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const float v = a[i];
+        bad = bad || !(v > 0.0f) || !(v < INFINITY);
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+__global__ void identity_P_kernel(double2 *P, int F, int M) {
+    const size_t n = static_cast<size_t>(F) * M * M;
+    for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const int e = static_cast<int>(i % (static_cast<size_t>(M) * M));
+        P[i] = make_double2(e / M == e % M ? 1.0 : 0.0, 0.0);
+    }
+}
+
+__global__ void fill_int_kernel(int *p, int n, int value) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
+}
+
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): the k-th output of the stream
+// seeded with s is mix(s + (k + 1) * 0x9E3779B97F4A7C15).
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ double unif24(uint64_t seed, uint64_t k) {
+    return static_cast<double>(splitmix64_at(seed, k) >> 40) * (1.0 / 16777216.0);
+}
+
+// One workgroup per frequency. lambda_nm = 0.5 + u;
+// v_tn = (|x_t|^2/(MN) + d_f)(0.5 + u'), d_f = 1e-6 mean_t |x_t|^2/(MN).
+__global__ void __launch_bounds__(kAuxThreads) seeded_init_kernel(const float2 *x, float *lam,
+                                                                  float *v, int T, int M, int N,
+                                                                  uint64_t seed, int do_lam,
+                                                                  int do_v) {
+    __shared__ double red[kAuxThreads / 64];
+    const int f = blockIdx.x;
+    const int tid = threadIdx.x;
+    const double inv_mn = 1.0 / (static_cast<double>(M) * N);
+    if (do_lam) {
+        for (int i = tid; i < N * M; i += blockDim.x)
+            lam[static_cast<size_t>(f) * N * M + i] = static_cast<float>(
+                0.5 + unif24(seed, static_cast<uint64_t>(f) * N * M + i));
+    }
+    if (!do_v) return;
+    const float2 *xf = x + static_cast<size_t>(f) * T * M;
+    double acc = 0.0;
+    for (int t = tid; t < T; t += blockDim.x) {
+        double p = 0.0;
+        for (int r = 0; r < M; ++r) {
+            const float2 e = xf[static_cast<size_t>(t) * M + r];
+            p += static_cast<double>(e.x) * e.x + static_cast<double>(e.y) * e.y;
+        }
+        acc += p * inv_mn;
+    }
+    acc = wave_sum(acc);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    double tot = 0.0;
+    for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) tot += red[w];
+    const double d = 1e-6 * tot / static_cast<double>(T);
+    for (int t = tid; t < T; t += blockDim.x) {
+        double p = 0.0;
+        for (int r = 0; r < M; ++r) {
+            const float2 e = xf[static_cast<size_t>(t) * M + r];
+            p += static_cast<double>(e.x) * e.x + static_cast<double>(e.y) * e.y;
+        }
+        p *= inv_mn;
+        for (int n = 0; n < N; ++n) {
+            const uint64_t k = (1ULL << 40) + (static_cast<uint64_t>(f) * T + t) * N + n;
+            v[(static_cast<size_t>(f) * T + t) * N + n] =
+                static_cast<float>((p + d) * (0.5 + unif24(seed, k)));
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+#define FFCA_M_SWITCH(M, CALL) \
+    switch (M) {               \
+        case 2: CALL(2); break; \
+        case 3: CALL(3); break; \
+        case 4: CALL(4); break; \
+        case 5: CALL(5); break; \
+        case 6: CALL(6); break; \
+        case 7: CALL(7); break; \
+        case 8: CALL(8); break; \
+        default: return hipErrorInvalidValue; \
+    }
+
+hipError_t launch_pinv(const WorkItem *items, int n_items, int M, float2 *Bh, double *ldet,
+                       hipStream_t s) {
+#define FFCA_CALL(MM) hipLaunchKernelGGL(pinv_kernel<MM>, dim3(n_items), dim3(64), 0, s, items, Bh, ldet)
+    FFCA_M_SWITCH(M, FFCA_CALL)
+#undef FFCA_CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_loglik_terms(const WorkItem *items, int n_items, int M, const double *ldet,
+                               double *ll_f, hipStream_t s) {
+#define FFCA_CALL(MM) \
+    hipLaunchKernelGGL(loglik_kernel<MM>, dim3(n_items), dim3(kAuxThreads), 0, s, items, ldet, ll_f)
+    FFCA_M_SWITCH(M, FFCA_CALL)
+#undef FFCA_CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_mwf_bins(const WorkItem *items, const float2 *Bh, int F, int T, int M,
+                           float2 *y, hipStream_t s) {
+    dim3 grid((T + kAuxThreads - 1) / kAuxThreads, F);
+#define FFCA_CALL(MM) hipLaunchKernelGGL(mwf_kernel<MM>, grid, dim3(kAuxThreads), 0, s, items, Bh, F, y)
+    FFCA_M_SWITCH(M, FFCA_CALL)
+#undef FFCA_CALL
+    return hipGetLastError();
+}
+
+static int grid_for(size_t n, int threads) {
+    size_t g = (n + threads - 1) / threads;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    return static_cast<int>(g);
+}
+
+hipError_t launch_check_finite_x(const float2 *x, size_t n, int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(check_finite_x_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, x, n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_positive(const float *a, size_t n, int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(check_positive_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, a, n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_identity_P(double2 *P, int F, int M, hipStream_t s) {
+    const size_t n = static_cast<size_t>(F) * M * M;
+    hipLaunchKernelGGL(identity_P_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, P, F, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int *p, int n, int value, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_seeded_init(const float2 *x, float *lam, float *v, int F, int T, int M, int N,
+                              uint64_t seed, bool do_lam, bool do_v, hipStream_t s) {
+    hipLaunchKernelGGL(seeded_init_kernel, dim3(F), dim3(kAuxThreads), 0, s, x, lam, v, T, M, N,
+                       seed, do_lam ? 1 : 0, do_v ? 1 : 0);
+    return hipGetLastError();
+}
+
+}  // namespace ffca

@@ -1,0 +1,186 @@
+// Device helpers for the FastFCA kernels (gfx950, 64-lane wavefronts).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ffca {
+
+// ----------------------------------------------------------------- wave sums
+// DPP controls (GFX9 encoding): quad_perm [1,0,3,2], quad_perm [2,3,0,1],
+// row_half_mirror, row_mirror. After the four steps every lane of a 16-lane
+// row holds the row sum (bitwise identical in every lane, IEEE addition being
+// commutative); the four row sums are then combined in a fixed order.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    long long b = __double_as_longlong(v);
+    int lo = dpp_i<CTRL>(static_cast<int>(b & 0xffffffffLL));
+    int hi = dpp_i<CTRL>(static_cast<int>(b >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                (static_cast<unsigned int>(lo)));
+}
+
+__device__ __forceinline__ float readlane_f(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    long long b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffffLL), l);
+    int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                (static_cast<unsigned int>(lo)));
+}
+
+// Sum over the 64 lanes of a wavefront; the result is wave-uniform.
+// Every lane must be active.
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp_f<0xB1>(v);
+    v += dpp_f<0x4E>(v);
+    v += dpp_f<0x141>(v);
+    v += dpp_f<0x140>(v);
+    return (readlane_f(v, 0) + readlane_f(v, 16)) + (readlane_f(v, 32) + readlane_f(v, 48));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// Single precision reciprocal (v_rcp_f32, about 1 ulp).
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// ----------------------------------------------------------------- complex fp64
+struct cd {
+    double re, im;
+};
+__device__ __forceinline__ cd cmk(double r, double i) { return cd{r, i}; }
+__device__ __forceinline__ cd operator+(cd a, cd b) { return cd{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cd operator-(cd a, cd b) { return cd{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cd operator*(cd a, cd b) {
+    return cd{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ cd operator*(double s, cd a) { return cd{s * a.re, s * a.im}; }
+__device__ __forceinline__ cd conjd(cd a) { return cd{a.re, -a.im}; }
+__device__ __forceinline__ double abs2(cd a) { return a.re * a.re + a.im * a.im; }
+__device__ __forceinline__ cd cdiv(cd a, cd b) {
+    // Smith's algorithm: avoids overflow of |b|^2 for large b.
+    if (fabs(b.re) >= fabs(b.im)) {
+        double r = b.im / b.re, d = b.re + b.im * r;
+        return cd{(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+    } else {
+        double r = b.re / b.im, d = b.re * r + b.im;
+        return cd{(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+    }
+}
+__device__ __forceinline__ cd ld(const double2 &a) { return cd{a.x, a.y}; }
+__device__ __forceinline__ double2 st(cd a) { return make_double2(a.re, a.im); }
+
+// Solve A z = b (M x M, complex double, in registers) by Gaussian elimination
+// with partial pivoting; z overwrites b. Pivot rows are swapped through
+// compile-time-indexed selects so the arrays stay in registers. Returns false
+// if a pivot falls below tol * max|A|.
+template <int M>
+__device__ __forceinline__ bool solve_pp(cd (&A)[M][M], cd (&b)[M], double tol) {
+    double amax2 = 0.0;
+#pragma unroll
+    for (int r = 0; r < M; ++r)
+#pragma unroll
+        for (int c = 0; c < M; ++c) amax2 = fmax(amax2, abs2(A[r][c]));
+    if (!(amax2 > 0.0) || !(amax2 < INFINITY)) return false;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        int p = k;
+        double best = abs2(A[k][k]);
+#pragma unroll
+        for (int i = k + 1; i < M; ++i) {
+            double a = abs2(A[i][k]);
+            if (a > best) {
+                best = a;
+                p = i;
+            }
+        }
+        if (!(best >= tol * tol * amax2)) return false;
+#pragma unroll
+        for (int i = k + 1; i < M; ++i) {
+            if (p == i) {
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    cd t = A[k][j];
+                    A[k][j] = A[i][j];
+                    A[i][j] = t;
+                }
+                cd t = b[k];
+                b[k] = b[i];
+                b[i] = t;
+            }
+        }
+#pragma unroll
+        for (int i = k + 1; i < M; ++i) {
+            cd l = cdiv(A[i][k], A[k][k]);
+#pragma unroll
+            for (int j = k; j < M; ++j) A[i][j] = A[i][j] - l * A[k][j];
+            b[i] = b[i] - l * b[k];
+        }
+    }
+#pragma unroll
+    for (int i = M - 1; i >= 0; --i) {
+        cd s = b[i];
+#pragma unroll
+        for (int j = i + 1; j < M; ++j) s = s - A[i][j] * b[j];
+        b[i] = cdiv(s, A[i][i]);
+    }
+    return true;
+}
+
+// ln|det A|^2 by elimination with partial pivoting (A is destroyed).
+template <int M>
+__device__ __forceinline__ double logabsdet2(cd (&A)[M][M]) {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        int p = k;
+        double best = abs2(A[k][k]);
+#pragma unroll
+        for (int i = k + 1; i < M; ++i) {
+            double a = abs2(A[i][k]);
+            if (a > best) {
+                best = a;
+                p = i;
+            }
+        }
+#pragma unroll
+        for (int i = k + 1; i < M; ++i) {
+            if (p == i) {
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    cd t = A[k][j];
+                    A[k][j] = A[i][j];
+                    A[i][j] = t;
+                }
+            }
+        }
+#pragma unroll
+        for (int i = k + 1; i < M; ++i) {
+            cd l = cdiv(A[i][k], A[k][k]);
+#pragma unroll
+            for (int j = k; j < M; ++j) A[i][j] = A[i][j] - l * A[k][j];
+        }
+        acc += log(abs2(A[k][k]));
+    }
+    return acc;
+}
+
+}  // namespace ffca

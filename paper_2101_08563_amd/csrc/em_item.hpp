@@ -1,0 +1,417 @@
+// FastFCA IP+EM iteration (Algorithm 1, Sec. IV-E) for gfx950.
+//
+// One workgroup owns one frequency of one mixture (every frequency is an
+// independent problem, Sec. II) and runs all requested iterations with the
+// frequency's state on chip:
+//   registers : x_t (M complex), h_t (N reals), U_t (M reals) for the
+//               bins this thread owns (t = tid + k * blockDim, k < BPT)
+//   LDS       : P in double precision, its single precision copy, reduction
+//               partials
+//   wave 0    : the double precision IP sweep (eq:ip1, eq:ip2) and ln|det P|^2
+// so HBM is touched once per call (read x, h, L, P; write h, L, P). Every
+// T-reduction is a fixed-order wavefront DPP tree followed by a fixed-order
+// sum over waves, so results are bitwise reproducible for a given launch
+// configuration.
+//
+// Per iteration (N + 2 workgroup barriers):
+//   A  sigma^2 = L H (eq:sigmadef), 1/sigma^2, and the M weighted
+//      covariances Q_m (eq:wsampcov) accumulated as the M*M real parameters of
+//      each Hermitian matrix; the same pass adds the log-likelihood terms of
+//      the previous iterate (eq:negll) using its U.
+//   IP wave 0: Q_m to double, sweep m = 1..M (eq:ip1, eq:ip2), ln|det P|^2.
+//   B  U_mt = |w_m^H x_t|^2 (eq:Udef).
+//   C  for n = 1..N in order: posterior gain and power (G_n, Phi_n), the
+//      T-reduction giving L[:,n] (with the old H[n,:]), then H[n,:] from the
+//      new L[:,n].
+#pragma once
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace ffca {
+
+constexpr int kMaxWaves = 16;       // 1024 threads
+constexpr int kMaxM = 4;            // resident family: M <= 4
+constexpr int kRedW = kMaxM * kMaxM * kMaxM;  // widest reduction (all Q_m, M = 4)
+constexpr double kLnPi = 1.1447298858494002;  // ln(pi)
+
+struct EmSmem {
+    float red[2][kMaxWaves][kRedW];
+    double red_d[2][kMaxWaves];
+    double qtot[kRedW];
+    double2 Pd[kMaxM * kMaxM];
+    float2 P32[kMaxM * kMaxM];
+    double2 Qm[kMaxM * kMaxM];   // IP scratch: Q_m as a full matrix
+    double2 A[kMaxM * kMaxM];    // IP scratch: P^H Q_m, then its elimination
+    double2 w[kMaxM];            // IP scratch: right-hand side / new column
+    int flag;
+};
+
+// IP sweep (Sec. IV-E): for m = 1..M in order, w_m <- (P^H Q_m)^{-1} e_m
+// (eq:ip1, Gaussian elimination with partial pivoting) and
+// w_m <- w_m / sqrt(w_m^H Q_m w_m) (eq:ip2); then ln|det P|^2. Run by every
+// lane of one wavefront on LDS-resident double precision matrices (all lanes
+// compute the same values, so the register footprint stays small and no lane
+// depends on another). Q_m arrives in sm.qtot as Hermitian real parameters,
+// already divided by T. Also refreshes the single precision copy sm.P32.
+template <int M>
+__device__ __forceinline__ int ip_sweep_lds(EmSmem &sm, double &ldet) {
+    double2 *P = sm.Pd;
+    double2 *Q = sm.Qm;
+    double2 *A = sm.A;
+    double2 *w = sm.w;
+#pragma unroll 1
+    for (int m = 0; m < M; ++m) {
+        const double *qm = sm.qtot + m * M * M;
+        bool finite = true;
+        for (int r = 0; r < M; ++r) {
+            Q[r * M + r] = make_double2(qm[r], 0.0);
+            finite = finite && fabs(qm[r]) < INFINITY;
+        }
+        {
+            int p = M;
+            for (int r = 0; r < M; ++r)
+                for (int c = r + 1; c < M; ++c) {
+                    Q[r * M + c] = make_double2(qm[p], qm[p + 1]);
+                    Q[c * M + r] = make_double2(qm[p], -qm[p + 1]);
+                    finite = finite && fabs(qm[p]) < INFINITY && fabs(qm[p + 1]) < INFINITY;
+                    p += 2;
+                }
+        }
+        if (!finite) return ST_NONFINITE;
+        // A = P^H Q_m
+        double amax2 = 0.0;
+        for (int r = 0; r < M; ++r)
+            for (int c = 0; c < M; ++c) {
+                cd s = cmk(0.0, 0.0);
+                for (int k = 0; k < M; ++k) s = s + conjd(ld(P[k * M + r])) * ld(Q[k * M + c]);
+                A[r * M + c] = st(s);
+                amax2 = fmax(amax2, abs2(s));
+            }
+        for (int r = 0; r < M; ++r) w[r] = make_double2(r == m ? 1.0 : 0.0, 0.0);
+        if (!(amax2 > 0.0) || !(amax2 < INFINITY)) return ST_SINGULAR;
+        // forward elimination with partial pivoting
+#pragma unroll 1
+        for (int k = 0; k < M; ++k) {
+            int piv = k;
+            double best = abs2(ld(A[k * M + k]));
+            for (int i = k + 1; i < M; ++i) {
+                const double a = abs2(ld(A[i * M + k]));
+                if (a > best) {
+                    best = a;
+                    piv = i;
+                }
+            }
+            if (!(best >= kPivotTol * kPivotTol * amax2)) return ST_SINGULAR;
+            if (piv != k) {
+                for (int j = 0; j < M; ++j) {
+                    const double2 t = A[k * M + j];
+                    A[k * M + j] = A[piv * M + j];
+                    A[piv * M + j] = t;
+                }
+                const double2 t = w[k];
+                w[k] = w[piv];
+                w[piv] = t;
+            }
+            const cd akk = ld(A[k * M + k]);
+            for (int i = k + 1; i < M; ++i) {
+                const cd l = cdiv(ld(A[i * M + k]), akk);
+                for (int j = k; j < M; ++j) A[i * M + j] = st(ld(A[i * M + j]) - l * ld(A[k * M + j]));
+                w[i] = st(ld(w[i]) - l * ld(w[k]));
+            }
+        }
+        for (int i = M - 1; i >= 0; --i) {
+            cd s = ld(w[i]);
+            for (int j = i + 1; j < M; ++j) s = s - ld(A[i * M + j]) * ld(w[j]);
+            w[i] = st(cdiv(s, ld(A[i * M + i])));
+        }
+        // normalization w^H Q_m w = 1
+        double qq = 0.0;
+        for (int r = 0; r < M; ++r) {
+            cd s = cmk(0.0, 0.0);
+            for (int c = 0; c < M; ++c) s = s + ld(Q[r * M + c]) * ld(w[c]);
+            qq += (conjd(ld(w[r])) * s).re;
+        }
+        if (!(qq > 0.0) || !(qq < INFINITY)) return ST_SINGULAR;
+        const double inv = 1.0 / sqrt(qq);
+        for (int r = 0; r < M; ++r) P[r * M + m] = st(inv * ld(w[r]));
+    }
+    // ln|det P|^2 by elimination of a copy
+    for (int i = 0; i < M * M; ++i) A[i] = P[i];
+    double acc = 0.0;
+#pragma unroll 1
+    for (int k = 0; k < M; ++k) {
+        int piv = k;
+        double best = abs2(ld(A[k * M + k]));
+        for (int i = k + 1; i < M; ++i) {
+            const double a = abs2(ld(A[i * M + k]));
+            if (a > best) {
+                best = a;
+                piv = i;
+            }
+        }
+        if (!(best > 0.0)) return ST_SINGULAR;
+        if (piv != k)
+            for (int j = 0; j < M; ++j) {
+                const double2 t = A[k * M + j];
+                A[k * M + j] = A[piv * M + j];
+                A[piv * M + j] = t;
+            }
+        const cd akk = ld(A[k * M + k]);
+        for (int i = k + 1; i < M; ++i) {
+            const cd l = cdiv(ld(A[i * M + k]), akk);
+            for (int j = k; j < M; ++j) A[i * M + j] = st(ld(A[i * M + j]) - l * ld(A[k * M + j]));
+        }
+        acc += log(best);
+    }
+    ldet = acc;
+    for (int i = 0; i < M * M; ++i)
+        sm.P32[i] = make_float2(static_cast<float>(P[i].x), static_cast<float>(P[i].y));
+    return ST_OK;
+}
+
+// Real parameters of a Hermitian M x M matrix: M diagonal entries, then
+// (re, im) of each upper-triangle entry (r < c) in row-major order.
+template <int M>
+__device__ __forceinline__ constexpr int herm_n() { return M * M; }
+
+template <int M, int N, int BPT>
+__device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, EmSmem &sm) {
+    constexpr int NQ = M * M * M;
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    const int nw = nthr >> 6;
+    const int T = it.T;
+    const float invTf = 1.0f / static_cast<float>(T);
+    const double invT = 1.0 / static_cast<double>(T);
+
+    // ---- load the frequency's state
+    float2 xr[BPT][M];
+    float vr[BPT][N];
+    float U[BPT][M];
+    bool valid[BPT];
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+        const int t = tid + k * nthr;
+        valid[k] = t < T;
+#pragma unroll
+        for (int r = 0; r < M; ++r) xr[k][r] = valid[k] ? it.x[t * M + r] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int n = 0; n < N; ++n) vr[k][n] = valid[k] ? it.v[t * N + n] : 1.0f;
+#pragma unroll
+        for (int m = 0; m < M; ++m) U[k][m] = 0.0f;
+    }
+    float lam[N][M];
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+        for (int m = 0; m < M; ++m) lam[n][m] = it.lam[n * M + m];
+    if (tid < M * M) {
+        sm.Pd[tid] = it.P[tid];
+    }
+    if (tid == 0) sm.flag = ST_OK;
+    __syncthreads();
+
+    double ldet_prev = 0.0;  // ln|det P|^2 of the iterate being evaluated (wave 0)
+    int buf = 0;
+    int status = ST_OK;
+
+    for (int iter = 0; iter <= n_iter; ++iter) {
+        const bool last = (iter == n_iter);
+        // ---------------- phase A: weights, Q_m, LL terms of the previous iterate
+        float q[NQ];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) q[i] = 0.0f;
+        double llp = 0.0;
+#pragma unroll
+        for (int k = 0; k < BPT; ++k) {
+            float w[M];
+            float s2[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                float s = 0.0f;
+#pragma unroll
+                for (int n = 0; n < N; ++n) s = fmaf(vr[k][n], lam[n][m], s);
+                s2[m] = s;
+                w[m] = rcp(s);
+            }
+            if (iter > 0 && valid[k]) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int m = 0; m < M; ++m) acc += __logf(s2[m]) + U[k][m] * w[m];
+                llp += static_cast<double>(acc);
+            }
+            if (!last) {
+                // Z_t = x_t x_t^H in Hermitian real parameters
+                float z[M * M];
+#pragma unroll
+                for (int r = 0; r < M; ++r)
+                    z[r] = xr[k][r].x * xr[k][r].x + xr[k][r].y * xr[k][r].y;
+                {
+                    int p = M;
+#pragma unroll
+                    for (int r = 0; r < M; ++r)
+#pragma unroll
+                        for (int c = r + 1; c < M; ++c) {
+                            z[p] = xr[k][r].x * xr[k][c].x + xr[k][r].y * xr[k][c].y;
+                            z[p + 1] = xr[k][r].y * xr[k][c].x - xr[k][r].x * xr[k][c].y;
+                            p += 2;
+                        }
+                }
+#pragma unroll
+                for (int m = 0; m < M; ++m)
+#pragma unroll
+                    for (int e = 0; e < M * M; ++e) q[m * M * M + e] = fmaf(w[m], z[e], q[m * M * M + e]);
+            }
+        }
+        // block reduction of Q (to wave 0) and of the LL partial
+        if (!last) {
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) q[i] = wave_sum(q[i]);
+        }
+        llp = wave_sum(llp);
+        if (lane == 0) {
+            if (!last) {
+#pragma unroll
+                for (int i = 0; i < NQ; ++i) sm.red[buf][wid][i] = q[i];
+            }
+            sm.red_d[buf][wid] = llp;
+        }
+        __syncthreads();
+        if (wid == 0) {
+            if (iter > 0) {
+                double s = 0.0;
+                for (int w = 0; w < nw; ++w) s += sm.red_d[buf][w];
+                const double ll = ldet_prev - static_cast<double>(M) * kLnPi - s * invT;
+                if (lane == 0) it.ll_trace[iter - 1] = ll;
+                if (!(ll == ll) || ll == INFINITY || ll == -INFINITY) status = ST_NONFINITE;
+            }
+            if (!last && status == ST_OK) {
+                if (lane < NQ) {
+                    float s = 0.0f;
+                    for (int w = 0; w < nw; ++w) s += sm.red[buf][w][lane];
+                    sm.qtot[lane] = static_cast<double>(s) * invT;
+                }
+                __threadfence_block();
+                __builtin_amdgcn_wave_barrier();
+                // ------------- IP sweep in double precision (LDS-resident matrices)
+                double ldet = 0.0;
+                status = ip_sweep_lds<M>(sm, ldet);
+                if (status == ST_OK) ldet_prev = ldet;
+            }
+            if (lane == 0) sm.flag = status;
+        }
+        if (last) break;
+        __syncthreads();
+        status = sm.flag;
+        if (status != ST_OK) break;
+        buf ^= 1;
+
+        // ---------------- phase B: U = |P^H x|^2
+        {
+            float2 Pw[M][M];
+#pragma unroll
+            for (int i = 0; i < M * M; ++i) Pw[i / M][i % M] = sm.P32[i];
+#pragma unroll
+            for (int k = 0; k < BPT; ++k) {
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    float yr = 0.0f, yi = 0.0f;
+#pragma unroll
+                    for (int r = 0; r < M; ++r) {
+                        // conj(P[r][m]) * x_r
+                        yr = fmaf(Pw[r][m].x, xr[k][r].x, yr);
+                        yr = fmaf(Pw[r][m].y, xr[k][r].y, yr);
+                        yi = fmaf(Pw[r][m].x, xr[k][r].y, yi);
+                        yi = fmaf(-Pw[r][m].y, xr[k][r].x, yi);
+                    }
+                    U[k][m] = yr * yr + yi * yi;
+                }
+            }
+        }
+
+        // ---------------- phase C: EM over sources, in order
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            if (status != ST_OK) continue;
+            float part[M];
+            float phi[BPT][M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) part[m] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < BPT; ++k) {
+                const float rv = rcp(vr[k][n]);
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    float s = 0.0f;
+#pragma unroll
+                    for (int nn = 0; nn < N; ++nn) s = fmaf(vr[k][nn], lam[nn][m], s);
+                    const float a = vr[k][n] * lam[n][m];
+                    const float g = a * rcp(s);
+                    const float ph = fmaf(g * g, U[k][m], (1.0f - g) * a);
+                    phi[k][m] = ph;
+                    part[m] += valid[k] ? ph * rv : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < M; ++m) part[m] = wave_sum(part[m]);
+            if (lane == 0) {
+#pragma unroll
+                for (int m = 0; m < M; ++m) sm.red[buf][wid][m] = part[m];
+            }
+            __syncthreads();
+            float rl[M];
+            bool good = true;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                float s = 0.0f;
+                for (int w = 0; w < nw; ++w) s += sm.red[buf][w][m];
+                const float l = s * invTf;
+                good = good && (l > 0.0f) && (l < INFINITY);
+                lam[n][m] = l;
+                rl[m] = rcp(l);
+            }
+            buf ^= 1;
+            if (!good) {
+                status = ST_NONFINITE;
+                continue;
+            }
+#pragma unroll
+            for (int k = 0; k < BPT; ++k) {
+                float s = 0.0f;
+#pragma unroll
+                for (int m = 0; m < M; ++m) s = fmaf(phi[k][m], rl[m], s);
+                vr[k][n] = valid[k] ? s * (1.0f / static_cast<float>(M)) : 1.0f;
+            }
+        }
+        if (status != ST_OK) break;
+    }
+
+    // ---- write back the state
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+        const int t = tid + k * nthr;
+        if (valid[k]) {
+#pragma unroll
+            for (int n = 0; n < N; ++n) it.v[t * N + n] = vr[k][n];
+        }
+    }
+    if (tid == 0) {
+#pragma unroll
+        for (int n = 0; n < N; ++n)
+#pragma unroll
+            for (int m = 0; m < M; ++m) it.lam[n * M + m] = lam[n][m];
+    }
+    if (wid == 0) {
+        if (lane < M * M) it.P[lane] = sm.Pd[lane];
+        if (lane == 0) {
+            *it.ldet = ldet_prev;
+            if (status != ST_OK) *it.status = status;
+        }
+    }
+    __syncthreads();  // the LDS is reused by the next item of a persistent launch
+}
+
+}  // namespace ffca

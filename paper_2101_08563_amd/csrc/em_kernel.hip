@@ -1,0 +1,113 @@
+// Kernels and dispatch of the IP+EM iteration; the per-item body is em_item.hpp.
+#include "em_item.hpp"
+
+namespace ffca {
+
+// Register budget: a launch with BPT bins per thread uses at most 2048 / BPT
+// threads (kMaxThreadsFor), which lets the compiler give each lane up to
+// 128 (BPT 2), 256 (BPT 4) or 512 (BPT 8) VGPRs.
+template <int M, int N, int BPT>
+__global__ void __launch_bounds__(kResidentBins / BPT) em_kernel(EmLaunch a) {
+    __shared__ EmSmem sm;
+    const WorkItem &it = a.items[blockIdx.x];
+    if (*it.status != ST_OK) return;  // frozen after an earlier failure
+    em_item<M, N, BPT>(it, a.n_iter, sm);
+}
+
+// ------------------------------------------------------------------ dispatch
+using EmFn = void (*)(EmLaunch);
+
+template <int M, int N>
+struct BptTable {
+    static EmFn get(int bpt) {
+        switch (bpt) {
+            case 2: return em_kernel<M, N, 2>;
+            case 4: return em_kernel<M, N, 4>;
+            case 8: return em_kernel<M, N, 8>;
+            default: return nullptr;
+        }
+    }
+};
+
+#define FFCA_N_CASES(M)                      \
+    switch (N) {                             \
+        case 2: return BptTable<M, 2>::get(bpt); \
+        case 3: return BptTable<M, 3>::get(bpt); \
+        case 4: return BptTable<M, 4>::get(bpt); \
+        case 5: return BptTable<M, 5>::get(bpt); \
+        case 6: return BptTable<M, 6>::get(bpt); \
+        case 7: return BptTable<M, 7>::get(bpt); \
+        case 8: return BptTable<M, 8>::get(bpt); \
+        default: return nullptr;             \
+    }
+
+static EmFn em_lookup(int M, int N, int bpt) {
+    switch (M) {
+        case 2: FFCA_N_CASES(2)
+        case 3: FFCA_N_CASES(3)
+        case 4: FFCA_N_CASES(4)
+        default: return nullptr;
+    }
+}
+
+bool em_supported(int M, int N, int bpt) { return em_lookup(M, N, bpt) != nullptr; }
+
+// Persistent launch over a mixed batch: every workgroup pulls the next work
+// item (one frequency of one mixture, longest first) from a device counter
+// and runs it with the (M, N) instantiation it needs. The grid drains when
+// the counter passes n_items.
+#define FFCA_PERSISTENT_CLASSES(X) X(2, 3) X(2, 4) X(3, 4) X(3, 5) X(4, 5) X(4, 6)
+
+template <int BPT>
+__global__ void __launch_bounds__(kResidentBins / BPT) em_persistent_kernel(EmLaunch a) {
+    __shared__ EmSmem sm;
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int i = s_item;
+        __syncthreads();
+        if (i >= a.n_items) break;
+        const WorkItem &it = a.items[i];
+        if (*it.status != ST_OK) continue;
+        switch (it.M * 16 + it.N) {
+#define FFCA_CASE(MM, NN) \
+    case MM * 16 + NN: em_item<MM, NN, BPT>(it, a.n_iter, sm); break;
+            FFCA_PERSISTENT_CLASSES(FFCA_CASE)
+#undef FFCA_CASE
+            default: break;
+        }
+    }
+}
+
+bool persistent_supported(int M, int N) {
+    switch (M * 16 + N) {
+#define FFCA_CASE(MM, NN) case MM * 16 + NN: return true;
+        FFCA_PERSISTENT_CLASSES(FFCA_CASE)
+#undef FFCA_CASE
+        default: return false;
+    }
+}
+
+hipError_t launch_em_persistent(const EmLaunch &a, int threads, int bpt, int grid, hipStream_t s) {
+    if (threads < 64 || threads * bpt > kResidentBins || (threads & 63) || !a.queue)
+        return hipErrorInvalidValue;
+    if (bpt == 4)
+        hipLaunchKernelGGL(em_persistent_kernel<4>, dim3(grid), dim3(threads), 0, s, a);
+    else if (bpt == 8)
+        hipLaunchKernelGGL(em_persistent_kernel<8>, dim3(grid), dim3(threads), 0, s, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_em(int M, int N, int bpt, int threads, const EmLaunch &a, int grid,
+                     hipStream_t s) {
+    EmFn fn = em_lookup(M, N, bpt);
+    if (!fn) return hipErrorInvalidValue;
+    if (threads < 64 || threads * bpt > kResidentBins || (threads & 63)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(threads), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace ffca

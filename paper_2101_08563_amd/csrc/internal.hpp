@@ -1,0 +1,69 @@
+// Internal declarations shared by the kernels and the host runtime of the
+// FastFCA library. Not part of the public ABI (include/fastfca.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ffca {
+
+// One unit of GPU work: one frequency of one mixture. Every array pointer
+// addresses that frequency's slice in the library's own buffers.
+struct WorkItem {
+    const float2 *x;   // [T][M]  mixture STFT
+    float *v;          // [T][N]  source powers h_{tn}
+    float *lam;        // [N][M]  diag(Lambda_n)
+    double2 *P;        // [M][M]  decorrelation matrix, double precision master
+    double *ll_trace;  // [trace_stride] LL per bin after each iteration
+    double *ldet;      // ln|det P|^2 after the last IP sweep
+    int *status;       // 0 = ok, else FASTFCA_E_* recorded by the kernel
+    int T, M, N;
+    int cls;           // kernel class index (M, N) used by the persistent launch
+};
+
+// Status codes written by kernels (mirror the public ABI values).
+enum : int { ST_OK = 0, ST_SINGULAR = -4, ST_NONFINITE = -5 };
+
+// Largest T handled by the resident IP+EM kernels: a workgroup holds at most
+// kResidentBins bins (threads * bins-per-thread), with threads <= 2048 / BPT.
+constexpr int kResidentBins = 2048;
+
+// Relative pivot threshold of the double precision IP solve.
+constexpr double kPivotTol = 1e-12;
+
+struct EmLaunch {
+    const WorkItem *items;  // items handled by this launch
+    int n_items;
+    int n_iter;
+    int *queue;             // persistent launch: next-item counter (nullptr otherwise)
+};
+
+// Launch one EM kernel (Algorithm 1 for n_iter iterations) over `n_items`
+// work items that share (M, N). bpt: bins per thread held in registers.
+hipError_t launch_em(int M, int N, int bpt, int threads, const EmLaunch &a, int grid,
+                     hipStream_t s);
+bool em_supported(int M, int N, int bpt);
+
+// Persistent launch over a mixed list of work items (any supported (M, N) in
+// the batch class table), pulling items from a device counter.
+hipError_t launch_em_persistent(const EmLaunch &a, int threads, int bpt, int grid,
+                                hipStream_t s);
+bool persistent_supported(int M, int N);
+
+// Double precision log-likelihood per frequency of one mixture.
+hipError_t launch_loglik(const WorkItem *items, int n_items, int M, double *ll_f,
+                         hipStream_t s);
+
+// Multichannel Wiener filter of one mixture: y [N][F][T][M].
+hipError_t launch_mwf(const WorkItem *items, int F, int T, int M, int N, float2 *y,
+                      hipStream_t s);
+
+// Initialization helpers.
+hipError_t launch_check_finite_x(const float2 *x, size_t n, int *flag, hipStream_t s);
+hipError_t launch_check_positive(const float *a, size_t n, int *flag, hipStream_t s);
+hipError_t launch_identity_P(double2 *P, int F, int M, hipStream_t s);
+hipError_t launch_seeded_init(const float2 *x, float *lam, float *v, int F, int T, int M,
+                              int N, uint64_t seed, bool do_lam, bool do_v, hipStream_t s);
+hipError_t launch_fill_int(int *p, int n, int value, hipStream_t s);
+
+}  // namespace ffca

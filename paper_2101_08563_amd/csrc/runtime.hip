@@ -1,0 +1,778 @@
+// Host runtime of the FastFCA library: context and buffer management,
+// validation, kernel dispatch, hipGraph replay of em_step, and the launch
+// configuration autotuner. Implements include/fastfca.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/fastfca.h"
+#include "internal.hpp"
+
+namespace ffca {
+hipError_t launch_pinv(const WorkItem *items, int n_items, int M, float2 *Bh, double *ldet,
+                       hipStream_t s);
+hipError_t launch_loglik_terms(const WorkItem *items, int n_items, int M, const double *ldet,
+                               double *ll_f, hipStream_t s);
+hipError_t launch_mwf_bins(const WorkItem *items, const float2 *Bh, int F, int T, int M,
+                           float2 *y, hipStream_t s);
+}  // namespace ffca
+
+using namespace ffca;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct Problem {
+    int F = 0, T = 0, M = 0, N = 0;
+    float2 *x = nullptr;
+    float *v = nullptr;
+    float *lam = nullptr;
+    double2 *P = nullptr;
+    double *ldet = nullptr;
+    double *llf = nullptr;
+    float2 *Bh = nullptr;
+    WorkItem *items = nullptr;  // this mixture's items in frequency order
+    int item0 = 0;  // index of frequency 0 in the context's item array
+};
+
+struct ClassCfg {
+    int M, N, Tmax;
+    int threads = 0, bpt = 0;
+    std::vector<int> items;  // item indices of this class, in launch order
+};
+
+}  // namespace
+
+struct fastfca_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::vector<Problem> probs;
+    std::vector<WorkItem> h_items;
+    WorkItem *d_items = nullptr;      // in launch order (grouped by class)
+    std::vector<int> item_pos;        // problem item index -> position in d_items
+    int *d_status = nullptr;
+    double *d_trace = nullptr;
+    int trace_cap = 0;
+    int last_n_iter = 0;
+    int *d_queue = nullptr;
+    std::vector<ClassCfg> classes;
+    std::vector<int> class_first;     // first position of each class in d_items
+    bool persistent = false;          // batch: one persistent launch
+    int p_threads = 0, p_bpt = 0, p_grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_n_iter = -1;
+    std::string err;
+    char arch[64] = {0};
+};
+
+namespace {
+
+int set_err(fastfca_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c)
+        c->err = buf;
+    else
+        g_init_error = buf;
+    return code;
+}
+
+#define HIPCHK(c, expr)                                                                     \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return set_err((c), FASTFCA_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+int dalloc(fastfca_ctx *c, T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) return FASTFCA_OK;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return set_err(c, FASTFCA_E_NOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
+                       hipGetErrorString(e));
+    }
+    return FASTFCA_OK;
+}
+
+void free_problem(Problem &p) {
+    hipFree(p.x);
+    hipFree(p.v);
+    hipFree(p.lam);
+    hipFree(p.P);
+    hipFree(p.ldet);
+    hipFree(p.llf);
+    hipFree(p.Bh);
+    hipFree(p.items);
+    p = Problem{};
+}
+
+void drop_graph(fastfca_ctx *c) {
+    if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+    c->graph_n_iter = -1;
+}
+
+// Smallest workgroup (multiple of 64) holding T bins at bpt bins per thread,
+// or 0 if it exceeds the kernel's thread limit 2048 / bpt.
+int threads_for(int T, int bpt) {
+    int th = ((T + bpt - 1) / bpt + 63) / 64 * 64;
+    if (th < 64) th = 64;
+    return th * bpt <= kResidentBins ? th : 0;
+}
+
+bool pick_default(int Tmax, int &threads, int &bpt) {
+    // about four bins per thread; two for short frames, eight if needed
+    for (int b : {4, 2, 8}) {
+        const int th = threads_for(Tmax, b);
+        if (th && (b != 2 || Tmax <= 128)) {
+            threads = th;
+            bpt = b;
+            return true;
+        }
+    }
+    return false;
+}
+
+int validate_shape(fastfca_ctx *c, int F, int T, int M, int N) {
+    if (F < 1 || T < 1 || M < 2 || N < 2)
+        return set_err(c, FASTFCA_E_ARG, "invalid shape F=%d T=%d M=%d N=%d (need F,T>=1, M,N>=2)",
+                       F, T, M, N);
+    if (T < M)
+        return set_err(c, FASTFCA_E_ARG, "T=%d < M=%d: the weighted covariances are singular", T, M);
+    if (M > FASTFCA_MAX_M || N > FASTFCA_MAX_N || T > FASTFCA_MAX_T)
+        return set_err(c, FASTFCA_E_UNSUPPORTED, "shape M=%d N=%d T=%d beyond the compiled limits", M,
+                       N, T);
+    return FASTFCA_OK;
+}
+
+// Builds classes, item order, device item array. Assumes problem buffers exist.
+int build_items(fastfca_ctx *c) {
+    std::map<std::pair<int, int>, int> cls_of;
+    c->classes.clear();
+    for (auto &p : c->probs) {
+        auto key = std::make_pair(p.M, p.N);
+        if (!cls_of.count(key)) {
+            cls_of[key] = static_cast<int>(c->classes.size());
+            ClassCfg cc;
+            cc.M = p.M;
+            cc.N = p.N;
+            cc.Tmax = 0;
+            c->classes.push_back(cc);
+        }
+        auto &cc = c->classes[cls_of[key]];
+        cc.Tmax = std::max(cc.Tmax, p.T);
+    }
+    int total = 0;
+    for (auto &p : c->probs) {
+        p.item0 = total;
+        total += p.F;
+    }
+    c->h_items.assign(total, WorkItem{});
+    for (size_t b = 0; b < c->probs.size(); ++b) {
+        auto &p = c->probs[b];
+        const int cls = cls_of[std::make_pair(p.M, p.N)];
+        for (int f = 0; f < p.F; ++f) {
+            WorkItem w{};
+            w.x = p.x + static_cast<size_t>(f) * p.T * p.M;
+            w.v = p.v + static_cast<size_t>(f) * p.T * p.N;
+            w.lam = p.lam + static_cast<size_t>(f) * p.N * p.M;
+            w.P = p.P + static_cast<size_t>(f) * p.M * p.M;
+            w.ldet = p.ldet + f;
+            w.T = p.T;
+            w.M = p.M;
+            w.N = p.N;
+            w.cls = cls;
+            c->h_items[p.item0 + f] = w;
+            c->classes[cls].items.push_back(p.item0 + f);
+        }
+    }
+    // longest items first inside each class (list scheduling)
+    for (auto &cc : c->classes)
+        std::stable_sort(cc.items.begin(), cc.items.end(), [&](int a, int b) {
+            return c->h_items[a].T > c->h_items[b].T;
+        });
+    for (auto &cc : c->classes) {
+        if (!pick_default(cc.Tmax, cc.threads, cc.bpt))
+            return set_err(c, FASTFCA_E_UNSUPPORTED, "T=%d too long for the resident kernels", cc.Tmax);
+        if (!em_supported(cc.M, cc.N, cc.bpt))
+            return set_err(c, FASTFCA_E_UNSUPPORTED, "no compiled kernel for M=%d N=%d", cc.M, cc.N);
+    }
+    int rc;
+    if ((rc = dalloc(c, &c->d_status, total)) != FASTFCA_OK) return rc;
+    if ((rc = dalloc(c, &c->d_items, total)) != FASTFCA_OK) return rc;
+    if ((rc = dalloc(c, &c->d_queue, 1)) != FASTFCA_OK) return rc;
+    HIPCHK(c, launch_fill_int(c->d_status, total, ST_OK, c->stream));
+    return FASTFCA_OK;
+}
+
+// (Re)allocates the LL trace and uploads the item array in launch order.
+int upload_items(fastfca_ctx *c, int n_iter) {
+    const int total = static_cast<int>(c->h_items.size());
+    if (n_iter > c->trace_cap || !c->d_trace) {
+        int cap = std::max(n_iter, 128);
+        hipFree(c->d_trace);
+        c->d_trace = nullptr;
+        int rc = dalloc(c, &c->d_trace, static_cast<size_t>(cap) * total);
+        if (rc != FASTFCA_OK) return rc;
+        c->trace_cap = cap;
+        drop_graph(c);
+    }
+    std::vector<WorkItem> ordered;
+    ordered.reserve(total);
+    c->item_pos.assign(total, 0);
+    c->class_first.clear();
+    auto push = [&](int i) {
+        WorkItem w = c->h_items[i];
+        w.ll_trace = c->d_trace + static_cast<size_t>(i) * c->trace_cap;
+        w.status = c->d_status + i;
+        c->item_pos[i] = static_cast<int>(ordered.size());
+        ordered.push_back(w);
+    };
+    if (c->persistent) {
+        // one queue over every item, costliest first (longest-processing-time
+        // list scheduling); cost ~ T * (M + N)
+        std::vector<int> order(total);
+        for (int i = 0; i < total; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            const auto &A = c->h_items[a], &B = c->h_items[b];
+            return static_cast<long>(A.T) * (A.M + A.N) > static_cast<long>(B.T) * (B.M + B.N);
+        });
+        for (int i : order) push(i);
+    } else {
+        for (auto &cc : c->classes) {
+            c->class_first.push_back(static_cast<int>(ordered.size()));
+            for (int i : cc.items) push(i);
+        }
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_items, ordered.data(), sizeof(WorkItem) * total,
+                             hipMemcpyHostToDevice, c->stream));
+    for (auto &p : c->probs) {
+        if (!p.items) {
+            int rc = dalloc(c, &p.items, p.F);
+            if (rc != FASTFCA_OK) return rc;
+        }
+        std::vector<WorkItem> own(p.F);
+        for (int f = 0; f < p.F; ++f) {
+            own[f] = c->h_items[p.item0 + f];
+            own[f].ll_trace = c->d_trace + static_cast<size_t>(p.item0 + f) * c->trace_cap;
+            own[f].status = c->d_status + p.item0 + f;
+        }
+        HIPCHK(c, hipMemcpyAsync(p.items, own.data(), sizeof(WorkItem) * p.F, hipMemcpyHostToDevice,
+                                 c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return FASTFCA_OK;
+}
+
+int alloc_problem(fastfca_ctx *c, Problem &p) {
+    int rc;
+    const size_t F = p.F, T = p.T, M = p.M, N = p.N;
+    if ((rc = dalloc(c, &p.x, F * T * M)) != FASTFCA_OK) return rc;
+    if ((rc = dalloc(c, &p.v, F * T * N)) != FASTFCA_OK) return rc;
+    if ((rc = dalloc(c, &p.lam, F * N * M)) != FASTFCA_OK) return rc;
+    if ((rc = dalloc(c, &p.P, F * M * M)) != FASTFCA_OK) return rc;
+    if ((rc = dalloc(c, &p.ldet, F)) != FASTFCA_OK) return rc;
+    if ((rc = dalloc(c, &p.llf, F)) != FASTFCA_OK) return rc;
+    if ((rc = dalloc(c, &p.Bh, F * M * M)) != FASTFCA_OK) return rc;
+    return FASTFCA_OK;
+}
+
+int init_problem(fastfca_ctx *c, Problem &p, const fastfca_problem &d, uint64_t seed, int b) {
+    const size_t F = p.F, T = p.T, M = p.M, N = p.N;
+    HIPCHK(c, hipMemcpyAsync(p.x, d.x, sizeof(float2) * F * T * M, hipMemcpyDeviceToDevice,
+                             c->stream));
+    int *flag = nullptr;
+    int rc = dalloc(c, &flag, 3);
+    if (rc != FASTFCA_OK) return rc;
+    int hflag[3] = {0, 0, 0};
+    hipError_t e = hipMemcpyAsync(flag, hflag, sizeof hflag, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_check_finite_x(p.x, F * T * M, flag, c->stream);
+    if (e == hipSuccess && d.lambda0) e = launch_check_positive(d.lambda0, F * N * M, flag + 1, c->stream);
+    if (e == hipSuccess && d.v0) e = launch_check_positive(d.v0, F * T * N, flag + 2, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    hipFree(flag);
+    if (e != hipSuccess) return set_err(c, FASTFCA_E_HIP, "validation failed: %s", hipGetErrorString(e));
+    if (hflag[0]) return set_err(c, FASTFCA_E_NONFINITE, "mixture %d: x holds NaN or Inf", b);
+    if (hflag[1]) return set_err(c, FASTFCA_E_ARG, "mixture %d: lambda0 must be finite and > 0", b);
+    if (hflag[2]) return set_err(c, FASTFCA_E_ARG, "mixture %d: v0 must be finite and > 0", b);
+    if (d.P0)
+        HIPCHK(c, hipMemcpyAsync(p.P, d.P0, sizeof(double2) * F * M * M, hipMemcpyDeviceToDevice,
+                                 c->stream));
+    else
+        HIPCHK(c, launch_identity_P(p.P, p.F, p.M, c->stream));
+    if (d.lambda0)
+        HIPCHK(c, hipMemcpyAsync(p.lam, d.lambda0, sizeof(float) * F * N * M,
+                                 hipMemcpyDeviceToDevice, c->stream));
+    if (d.v0)
+        HIPCHK(c, hipMemcpyAsync(p.v, d.v0, sizeof(float) * F * T * N, hipMemcpyDeviceToDevice,
+                                 c->stream));
+    if (!d.lambda0 || !d.v0)
+        HIPCHK(c, launch_seeded_init(p.x, p.lam, p.v, p.F, p.T, p.M, p.N, seed, !d.lambda0, !d.v0,
+                                     c->stream));
+    return FASTFCA_OK;
+}
+
+int create(fastfca_ctx **out, int B, const fastfca_problem *probs, uint64_t seed, void *stream) {
+    if (!out) return set_err(nullptr, FASTFCA_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (B < 1 || !probs) return set_err(nullptr, FASTFCA_E_ARG, "need B >= 1 problems");
+    for (int b = 0; b < B; ++b) {
+        const auto &d = probs[b];
+        int rc = validate_shape(nullptr, d.F, d.T, d.M, d.N);
+        if (rc != FASTFCA_OK) {
+            g_init_error = "mixture " + std::to_string(b) + ": " + g_init_error;
+            return rc;
+        }
+        if (!d.x) return set_err(nullptr, FASTFCA_E_ARG, "mixture %d: x is NULL", b);
+    }
+    auto *c = new fastfca_ctx();
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    hipGetDevice(&c->device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess)
+        snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
+    c->probs.resize(B);
+    int rc = FASTFCA_OK;
+    for (int b = 0; b < B && rc == FASTFCA_OK; ++b) {
+        auto &p = c->probs[b];
+        p.F = probs[b].F;
+        p.T = probs[b].T;
+        p.M = probs[b].M;
+        p.N = probs[b].N;
+        rc = alloc_problem(c, p);
+        if (rc == FASTFCA_OK) rc = init_problem(c, p, probs[b], seed + static_cast<uint64_t>(b), b);
+    }
+    if (rc == FASTFCA_OK) rc = build_items(c);
+    if (rc == FASTFCA_OK) {
+        c->persistent = B > 1;
+        if (c->persistent) {
+            // one persistent launch: the widest class sets the block shape
+            int Tmax = 0;
+            bool ok = true;
+            for (auto &cc : c->classes) {
+                Tmax = std::max(Tmax, cc.Tmax);
+                ok = ok && persistent_supported(cc.M, cc.N);
+            }
+            if (!ok || !pick_default(Tmax, c->p_threads, c->p_bpt)) c->persistent = false;
+            if (c->persistent && c->p_bpt == 2) c->p_bpt = 4;
+            int ncu = 256;
+            if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) !=
+                hipSuccess)
+                ncu = 256;
+            c->p_grid = ncu * std::max(1, 2048 / c->p_threads);
+        }
+        rc = upload_items(c, 128);
+    }
+    if (rc == FASTFCA_OK) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) rc = set_err(c, FASTFCA_E_HIP, "init: %s", hipGetErrorString(e));
+    }
+    if (rc != FASTFCA_OK) {
+        g_init_error = c->err;
+        fastfca_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return FASTFCA_OK;
+}
+
+int record_em(fastfca_ctx *c, int n_iter) {
+    if (c->persistent) {
+        HIPCHK(c, launch_fill_int(c->d_queue, 1, 0, c->stream));
+        EmLaunch a{c->d_items, static_cast<int>(c->h_items.size()), n_iter, c->d_queue};
+        HIPCHK(c, launch_em_persistent(a, c->p_threads, c->p_bpt, c->p_grid, c->stream));
+        return FASTFCA_OK;
+    }
+    for (size_t k = 0; k < c->classes.size(); ++k) {
+        const auto &cc = c->classes[k];
+        EmLaunch a{c->d_items + c->class_first[k], static_cast<int>(cc.items.size()), n_iter,
+                   nullptr};
+        HIPCHK(c, launch_em(cc.M, cc.N, cc.bpt, cc.threads, a, static_cast<int>(cc.items.size()),
+                            c->stream));
+    }
+    return FASTFCA_OK;
+}
+
+int check_status(fastfca_ctx *c) {
+    const int total = static_cast<int>(c->h_items.size());
+    std::vector<int> st(total);
+    HIPCHK(c, hipMemcpyAsync(st.data(), c->d_status, sizeof(int) * total, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t b = 0; b < c->probs.size(); ++b) {
+        const auto &p = c->probs[b];
+        for (int f = 0; f < p.F; ++f) {
+            const int s = st[p.item0 + f];
+            if (s != ST_OK)
+                return set_err(c, s, "mixture %zu frequency %d: %s", b, f,
+                               s == ST_SINGULAR ? "IP system numerically singular"
+                                                : "non-finite value in an iterate");
+        }
+    }
+    return FASTFCA_OK;
+}
+
+bool valid_problem(fastfca_ctx *c, int b) { return c && b >= 0 && b < static_cast<int>(c->probs.size()); }
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+int fastfca_init(fastfca_ctx **out, const fastfca_c64 *x, int F, int T, int M, int N,
+                 const fastfca_c128 *P0, const float *lambda0, const float *v0, uint64_t seed,
+                 void *hip_stream) {
+    fastfca_problem d{x, F, T, M, N, P0, lambda0, v0};
+    return create(out, 1, &d, seed, hip_stream);
+}
+
+int fastfca_init_batch(fastfca_ctx **out, int B, const fastfca_problem *probs, uint64_t seed,
+                       void *hip_stream) {
+    return create(out, B, probs, seed, hip_stream);
+}
+
+int fastfca_em_step(fastfca_ctx *c, int n_iter) {
+    if (!c) return FASTFCA_E_ARG;
+    if (n_iter < 1) return set_err(c, FASTFCA_E_ARG, "n_iter must be >= 1");
+    if (n_iter > c->trace_cap) {
+        int rc = upload_items(c, n_iter);
+        if (rc != FASTFCA_OK) return rc;
+    }
+    c->last_n_iter = n_iter;
+    if (c->graph_exec && c->graph_n_iter == n_iter) {
+        HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+        return FASTFCA_OK;
+    }
+    drop_graph(c);
+    // capture the launch sequence once per n_iter, replay on later calls
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        int rc = record_em(c, n_iter);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+        if (rc != FASTFCA_OK) {
+            if (g) hipGraphDestroy(g);
+            return rc;
+        }
+        if (e2 == hipSuccess && g) {
+            hipGraphExec_t ge = nullptr;
+            if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess) {
+                c->graph = g;
+                c->graph_exec = ge;
+                c->graph_n_iter = n_iter;
+                HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+                return FASTFCA_OK;
+            }
+            hipGraphDestroy(g);
+        }
+        (void)hipGetLastError();
+    } else {
+        (void)hipGetLastError();
+    }
+    // capture unavailable (e.g. legacy default stream): launch directly
+    return record_em(c, n_iter);
+}
+
+int fastfca_sync(fastfca_ctx *c) {
+    if (!c) return FASTFCA_E_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return check_status(c);
+}
+
+int fastfca_loglik(fastfca_ctx *c, int b, double *ll_per_bin, double *ll_per_f) {
+    if (!valid_problem(c, b)) return c ? set_err(c, FASTFCA_E_ARG, "bad mixture index %d", b) : FASTFCA_E_ARG;
+    auto &p = c->probs[b];
+    hipError_t e = launch_pinv(p.items, p.F, p.M, nullptr, p.ldet, c->stream);
+    if (e == hipSuccess) e = launch_loglik_terms(p.items, p.F, p.M, p.ldet, p.llf, c->stream);
+    std::vector<double> llf(p.F);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(llf.data(), p.llf, sizeof(double) * p.F, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && ll_per_f)
+        e = hipMemcpyAsync(ll_per_f, p.llf, sizeof(double) * p.F, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return set_err(c, FASTFCA_E_HIP, "loglik: %s", hipGetErrorString(e));
+    int rc = check_status(c);
+    if (rc != FASTFCA_OK) return rc;
+    double s = 0.0;
+    for (double v : llf) s += v;
+    if (ll_per_bin) *ll_per_bin = s / p.F;
+    if (!std::isfinite(s)) return set_err(c, FASTFCA_E_NONFINITE, "mixture %d: non-finite log-likelihood", b);
+    return FASTFCA_OK;
+}
+
+int fastfca_ll_trace(fastfca_ctx *c, int b, double *trace, int max_n) {
+    if (!valid_problem(c, b) || !trace || max_n < 0) return c ? set_err(c, FASTFCA_E_ARG, "bad arguments") : FASTFCA_E_ARG;
+    if (c->last_n_iter == 0) return 0;
+    auto &p = c->probs[b];
+    const int n = std::min(max_n, c->last_n_iter);
+    std::vector<double> buf(static_cast<size_t>(p.F) * c->trace_cap);
+    HIPCHK(c, hipMemcpyAsync(buf.data(), c->d_trace + static_cast<size_t>(p.item0) * c->trace_cap,
+                             sizeof(double) * buf.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int rc = check_status(c);
+    if (rc != FASTFCA_OK) return rc;
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int f = 0; f < p.F; ++f) s += buf[static_cast<size_t>(f) * c->trace_cap + i];
+        trace[i] = s / p.F;
+    }
+    return n;
+}
+
+int fastfca_mwf(fastfca_ctx *c, int b, fastfca_c64 *y) {
+    if (!valid_problem(c, b) || !y) return c ? set_err(c, FASTFCA_E_ARG, "bad arguments") : FASTFCA_E_ARG;
+    auto &p = c->probs[b];
+    HIPCHK(c, launch_pinv(p.items, p.F, p.M, p.Bh, p.ldet, c->stream));
+    HIPCHK(c, launch_mwf_bins(p.items, p.Bh, p.F, p.T, p.M, reinterpret_cast<float2 *>(y), c->stream));
+    return FASTFCA_OK;
+}
+
+int fastfca_get_params(fastfca_ctx *c, int b, fastfca_c128 *P, float *lambda, float *v) {
+    if (!valid_problem(c, b)) return c ? set_err(c, FASTFCA_E_ARG, "bad mixture index %d", b) : FASTFCA_E_ARG;
+    auto &p = c->probs[b];
+    const size_t F = p.F, T = p.T, M = p.M, N = p.N;
+    if (P) HIPCHK(c, hipMemcpyAsync(P, p.P, sizeof(double2) * F * M * M, hipMemcpyDeviceToDevice, c->stream));
+    if (lambda)
+        HIPCHK(c, hipMemcpyAsync(lambda, p.lam, sizeof(float) * F * N * M, hipMemcpyDeviceToDevice, c->stream));
+    if (v) HIPCHK(c, hipMemcpyAsync(v, p.v, sizeof(float) * F * T * N, hipMemcpyDeviceToDevice, c->stream));
+    return FASTFCA_OK;
+}
+
+int fastfca_shape(const fastfca_ctx *c, int b, int *F, int *T, int *M, int *N) {
+    if (!c || b < 0 || b >= static_cast<int>(c->probs.size())) return FASTFCA_E_ARG;
+    const auto &p = c->probs[b];
+    if (F) *F = p.F;
+    if (T) *T = p.T;
+    if (M) *M = p.M;
+    if (N) *N = p.N;
+    return FASTFCA_OK;
+}
+
+int fastfca_num_problems(const fastfca_ctx *c) { return c ? static_cast<int>(c->probs.size()) : FASTFCA_E_ARG; }
+
+int fastfca_set_config(fastfca_ctx *c, int threads, int bins_per_thread) {
+    if (!c) return FASTFCA_E_ARG;
+    if (threads == 0 && bins_per_thread == 0) {
+        for (auto &cc : c->classes) pick_default(cc.Tmax, cc.threads, cc.bpt);
+        drop_graph(c);
+        return FASTFCA_OK;
+    }
+    if (threads < 64 || (threads & 63) || threads * bins_per_thread > kResidentBins ||
+        (bins_per_thread != 2 && bins_per_thread != 4 && bins_per_thread != 8))
+        return set_err(c, FASTFCA_E_ARG, "invalid config threads=%d bins_per_thread=%d", threads,
+                       bins_per_thread);
+    for (auto &cc : c->classes)
+        if (threads * bins_per_thread < cc.Tmax)
+            return set_err(c, FASTFCA_E_ARG, "threads*bins_per_thread=%d < T=%d",
+                           threads * bins_per_thread, cc.Tmax);
+    if (c->persistent) {
+        c->p_threads = threads;
+        c->p_bpt = bins_per_thread;
+    } else {
+        for (auto &cc : c->classes) {
+            cc.threads = threads;
+            cc.bpt = bins_per_thread;
+        }
+    }
+    drop_graph(c);
+    return FASTFCA_OK;
+}
+
+int fastfca_get_config(const fastfca_ctx *c, int b, int *threads, int *bins_per_thread) {
+    if (!c || b < 0 || b >= static_cast<int>(c->probs.size())) return FASTFCA_E_ARG;
+    if (c->persistent) {
+        if (threads) *threads = c->p_threads;
+        if (bins_per_thread) *bins_per_thread = c->p_bpt;
+        return FASTFCA_OK;
+    }
+    const auto &p = c->probs[b];
+    for (const auto &cc : c->classes)
+        if (cc.M == p.M && cc.N == p.N) {
+            if (threads) *threads = cc.threads;
+            if (bins_per_thread) *bins_per_thread = cc.bpt;
+            return FASTFCA_OK;
+        }
+    return FASTFCA_E_STATE;
+}
+
+int fastfca_autotune(fastfca_ctx *c, int n_iter, const char *cache_path) {
+    if (!c || n_iter < 1) return c ? set_err(c, FASTFCA_E_ARG, "n_iter must be >= 1") : FASTFCA_E_ARG;
+    int rc = fastfca_sync(c);
+    if (rc != FASTFCA_OK) return rc;
+    if (n_iter > c->trace_cap && (rc = upload_items(c, n_iter)) != FASTFCA_OK) return rc;
+    // snapshot the state: trials run on the live buffers and are undone
+    struct Snap {
+        float *v, *lam;
+        double2 *P;
+    };
+    std::vector<Snap> snaps(c->probs.size(), Snap{nullptr, nullptr, nullptr});
+    auto free_snaps = [&]() {
+        for (auto &s : snaps) {
+            hipFree(s.v);
+            hipFree(s.lam);
+            hipFree(s.P);
+        }
+    };
+    for (size_t b = 0; b < c->probs.size() && rc == FASTFCA_OK; ++b) {
+        auto &p = c->probs[b];
+        const size_t F = p.F, T = p.T, M = p.M, N = p.N;
+        if ((rc = dalloc(c, &snaps[b].v, F * T * N)) != FASTFCA_OK) break;
+        if ((rc = dalloc(c, &snaps[b].lam, F * N * M)) != FASTFCA_OK) break;
+        if ((rc = dalloc(c, &snaps[b].P, F * M * M)) != FASTFCA_OK) break;
+        hipMemcpyAsync(snaps[b].v, p.v, sizeof(float) * F * T * N, hipMemcpyDeviceToDevice, c->stream);
+        hipMemcpyAsync(snaps[b].lam, p.lam, sizeof(float) * F * N * M, hipMemcpyDeviceToDevice, c->stream);
+        hipMemcpyAsync(snaps[b].P, p.P, sizeof(double2) * F * M * M, hipMemcpyDeviceToDevice, c->stream);
+    }
+    if (rc != FASTFCA_OK) {
+        free_snaps();
+        return rc;
+    }
+    auto restore = [&]() {
+        for (size_t b = 0; b < c->probs.size(); ++b) {
+            auto &p = c->probs[b];
+            const size_t F = p.F, T = p.T, M = p.M, N = p.N;
+            hipMemcpyAsync(p.v, snaps[b].v, sizeof(float) * F * T * N, hipMemcpyDeviceToDevice, c->stream);
+            hipMemcpyAsync(p.lam, snaps[b].lam, sizeof(float) * F * N * M, hipMemcpyDeviceToDevice, c->stream);
+            hipMemcpyAsync(p.P, snaps[b].P, sizeof(double2) * F * M * M, hipMemcpyDeviceToDevice, c->stream);
+        }
+        launch_fill_int(c->d_status, static_cast<int>(c->h_items.size()), ST_OK, c->stream);
+    };
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    auto time_once = [&](float &ms) -> int {
+        restore();
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        int r = record_em(c, n_iter);
+        if (r != FASTFCA_OK) return r;
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        return FASTFCA_OK;
+    };
+    auto best_of = [&](float &best) -> int {
+        best = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            float ms = 0.f;
+            int r = time_once(ms);
+            if (r != FASTFCA_OK) return r;
+            best = std::min(best, ms);
+        }
+        return FASTFCA_OK;
+    };
+    FILE *cache = cache_path ? fopen(cache_path, "a") : nullptr;
+    auto bucket = [](int T) {
+        int b = 64;
+        while (b < T) b <<= 1;
+        return b;
+    };
+    if (c->persistent) {
+        int ncu = 256;
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+        int Tmax = 0;
+        for (auto &cc : c->classes) Tmax = std::max(Tmax, cc.Tmax);
+        int bt = c->p_threads, bb = c->p_bpt, bg = c->p_grid;
+        float best = 1e30f;
+        for (int bpt : {4, 8}) {
+            const int th = threads_for(Tmax, bpt);
+            if (!th) continue;
+            for (int per_cu : {1, 2, 4}) {
+                c->p_threads = th;
+                c->p_bpt = bpt;
+                c->p_grid = ncu * per_cu;
+                float ms;
+                rc = best_of(ms);
+                if (rc != FASTFCA_OK) break;
+                if (ms < best) {
+                    best = ms;
+                    bt = th;
+                    bb = bpt;
+                    bg = c->p_grid;
+                }
+            }
+            if (rc != FASTFCA_OK) break;
+        }
+        c->p_threads = bt;
+        c->p_bpt = bb;
+        c->p_grid = bg;
+        if (cache && rc == FASTFCA_OK)
+            fprintf(cache,
+                    "{\"arch\": \"%s\", \"kind\": \"persistent\", \"items\": %zu, \"Tbucket\": %d, "
+                    "\"threads\": %d, \"bins_per_thread\": %d, \"grid\": %d, \"ms\": %.6f}\n",
+                    c->arch, c->h_items.size(), bucket(Tmax), bt, bb, bg, best);
+    } else {
+        for (auto &cc : c->classes) {
+            int bt = cc.threads, bb = cc.bpt;
+            float best = 1e30f;
+            for (int bpt : {2, 4, 8}) {
+                const int th = threads_for(cc.Tmax, bpt);
+                if (!th || !em_supported(cc.M, cc.N, bpt)) continue;
+                cc.threads = th;
+                cc.bpt = bpt;
+                float ms;
+                rc = best_of(ms);
+                if (rc != FASTFCA_OK) break;
+                if (ms < best) {
+                    best = ms;
+                    bt = th;
+                    bb = bpt;
+                }
+            }
+            cc.threads = bt;
+            cc.bpt = bb;
+            if (rc != FASTFCA_OK) break;
+            if (cache)
+                fprintf(cache,
+                        "{\"arch\": \"%s\", \"kind\": \"class\", \"M\": %d, \"N\": %d, \"Tbucket\": %d, "
+                        "\"threads\": %d, \"bins_per_thread\": %d, \"ms\": %.6f}\n",
+                        c->arch, cc.M, cc.N, bucket(cc.Tmax), bt, bb, best);
+        }
+    }
+    if (cache) fclose(cache);
+    restore();
+    hipError_t e = hipStreamSynchronize(c->stream);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    free_snaps();
+    drop_graph(c);
+    if (rc == FASTFCA_OK && e != hipSuccess)
+        rc = set_err(c, FASTFCA_E_HIP, "autotune: %s", hipGetErrorString(e));
+    return rc;
+}
+
+const char *fastfca_last_error(const fastfca_ctx *c) {
+    return c ? c->err.c_str() : g_init_error.c_str();
+}
+
+void fastfca_destroy(fastfca_ctx *c) {
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    drop_graph(c);
+    for (auto &p : c->probs) free_problem(p);
+    hipFree(c->d_items);
+    hipFree(c->d_status);
+    hipFree(c->d_trace);
+    hipFree(c->d_queue);
+    delete c;
+}
+
+}  // extern "C"
