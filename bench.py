@@ -1,0 +1,182 @@
+"""Benchmark of the FastFCA hot path on one MI355X.
+
+One step = one pass of the whole path over the headline workload (M=2 mics,
+N=3 sources, F=513 bins, T=1000 frames; synthetic mixture drawn by
+paper_2101_08563_amd.synth): set the initial parameters (Algorithm 1,
+initialize), 100 IP+EM iterations with the per-iteration log-likelihood
+(Algorithm 1, eq:negll), and the multichannel Wiener filter (eq:Doclo).
+Inputs are resident in HBM before timing starts.
+
+Metric: EM TF-bin*source updates per second = F*T*N*iterations / step time.
+
+Prints ONE JSON line (see the fields below). Options:
+  --gpus N (only 1 is supported), --steps K, --warmup W, --iters I,
+  --no-cpu (skip the oracle CPU baseline), --calib-copy MiB (also run a plain
+  device copy of that size, used to scale rocprofv3 byte counters).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X figures used for the roofline (per-unit derivations in the design doc).
+CU, SIMD_PER_CU, LANES, CLOCK_HZ = 256, 4, 16, 2.4e9
+FP32_FMA_PEAK = CU * SIMD_PER_CU * LANES * 2 * CLOCK_HZ      # 78.6 TFLOP/s, non-packed FP32 FMA
+HBM_PEAK = 8.0e12                                            # bytes/s
+
+
+def em_flops_per_bin(M: int, N: int) -> int:
+    """Algorithmic flops per TF bin per IP+EM iteration (FMA = 2 flops):
+    sigma^2 and its inverse (2MN + M), x x^H as M^2 real parameters (3M^2),
+    the M weighted covariances (2M^3), U = |P^H x|^2 (8M^2 + 3M), the N
+    sequential source updates (N (2MN + 12M + 2)), the log-likelihood terms (4M)."""
+    return (2 * M * N + M) + 3 * M * M + 2 * M ** 3 + (8 * M * M + 3 * M) \
+        + N * (2 * M * N + 12 * M + 2) + 4 * M
+
+
+def em_bytes_per_bin(M: int, N: int) -> int:
+    """Algorithmic HBM bytes per TF bin per launch: read x (8M), read and write v (8N)."""
+    return 8 * M + 8 * N
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--iters", type=int, default=100)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy", type=int, default=0)
+    ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--bpt", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build measures the single-GPU kernel "
+              "(frequencies shard across GPUs with no exchange; see the design notes). "
+              "--gpus %d is not supported." % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2101_08563_amd import FastFCA, synth
+
+    cfg = synth.CONFIGS["c1"]
+    F, T, M, N = cfg["F"], cfg["T"], cfg["M"], cfg["N"]
+    iters = args.iters
+    x = synth.mixture(F=F, T=T, M=M, N=N, rank=cfg["rank"], diffuse=cfg["diffuse"],
+                      config_id=cfg["config_id"])
+    P0, lam0, v0 = synth.init_params(x, N, config_id=cfg["config_id"])
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        xd = torch.from_numpy(x).to(dev)
+        Pd = torch.from_numpy(P0).to(dev)
+        ld = torch.from_numpy(lam0).to(dev)
+        vd = torch.from_numpy(v0).to(dev)
+        y = torch.empty((N, F, T, M), dtype=torch.complex64, device=dev)
+    stream.synchronize()
+    ctx = FastFCA(xd, N, Pd, ld, vd, stream=stream)
+    if args.threads:
+        ctx.set_config(args.threads, args.bpt)
+    threads, bpt = ctx.get_config()
+
+    def step(ev=None):
+        ctx.set_params(Pd, ld, vd)
+        if ev is not None:
+            ev[0].record(stream)
+        ctx.em_step(iters)
+        if ev is not None:
+            ev[1].record(stream)
+        ctx.mwf(out=y)
+
+    for _ in range(args.warmup):
+        step()
+    ctx.sync()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.sync()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    em_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    trace = ctx.ll_trace()
+    ll = ctx.loglik()
+    assert np.isfinite(ll) and len(trace) == iters
+
+    updates = F * T * N * iters
+    value = updates / (ms_per_step * 1e-3)
+    flops = em_flops_per_bin(M, N) * F * T * iters
+    achieved = flops / (em_ms * 1e-3)
+    hbm_bytes = em_bytes_per_bin(M, N) * F * T
+    out = {
+        "metric": "EM TF-bin*source updates/s",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "FastFCA IP+EM x%d + MWF, M=%d N=%d F=%d T=%d" % (iters, M, N, F, T),
+                   "M": M, "N": N, "F": F, "T": T, "iters": iters, "threads": threads,
+                   "bins_per_thread": bpt, "ll_per_bin": ll},
+        "roofline": {
+            "kernel": "em_kernel<%d,%d,%d> (IP+EM, state resident on chip)" % (M, N, bpt),
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": FP32_FMA_PEAK / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_FMA_PEAK,
+            "traffic": None,
+            "em_ms_per_launch": em_ms,
+            "flops_per_launch": flops,
+            "hbm_algorithmic_bytes_per_launch": hbm_bytes,
+            "hbm_GBps_algorithmic": hbm_bytes / (em_ms * 1e-3) / 1e9,
+        },
+    }
+    if args.calib_copy:
+        n = args.calib_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = 2 * n * 4
+
+    if not args.no_cpu:
+        import oracle
+        t2 = time.perf_counter()
+        Po, lo, vo, _ = oracle.fit(x, P0, lam0, v0, iters)
+        oracle.mwf(x, Po, lo, vo)
+        t3 = time.perf_counter()
+        out["cpu_baseline"] = {
+            "value": updates / (t3 - t2),
+            "unit": "updates/s",
+            "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "full workload: F=%d T=%d M=%d N=%d, %d IP+EM iterations + MWF, FP64 C, OpenMP over "
+                      "frequencies, %.2f s" % (F, T, M, N, iters, t3 - t2),
+        }
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -155,6 +155,17 @@ int fastfca_mwf(fastfca_ctx *c, int b, fastfca_c64 *y);
  */
 int fastfca_get_params(fastfca_ctx *c, int b, fastfca_c128 *P, float *lambda, float *v);
 
+/*
+ * fastfca_set_params -- overwrite the current (P, lambda, v) of mixture b
+ * from caller device buffers (layouts above; any pointer may be NULL to keep
+ * that parameter), i.e. re-run Algorithm 1's "Initialize W, L, H" with given
+ * values: restarts, checkpoint resume, warm starts. Clears the recorded
+ * failure state of the mixture. Values are not validated (lambda and v must
+ * be finite and > 0). Stream-ordered (asynchronous).
+ */
+int fastfca_set_params(fastfca_ctx *c, int b, const fastfca_c128 *P, const float *lambda,
+                       const float *v);
+
 /* Shape of mixture b: writes F, T, M, N (host pointers; any may be NULL). */
 int fastfca_shape(const fastfca_ctx *c, int b, int *F, int *T, int *M, int *N);
 
@@ -164,8 +175,9 @@ int fastfca_num_problems(const fastfca_ctx *c);
 /*
  * fastfca_set_config -- override the launch configuration of every
  * subsequent fastfca_em_step: threads per workgroup (64..1024, multiple of
- * 64, or 0 = autotuned/default) and bins per thread (2, 4 or 8, or 0). The
- * pair must cover the longest T of every (M,N) class; E_ARG otherwise.
+ * 64, or 0 = default) and bins per thread (2, 4, 8 or 16; 0 = default).
+ * threads * bins_per_thread must cover the longest T of every (M,N) class and
+ * may not exceed 2048; E_ARG otherwise.
  */
 int fastfca_set_config(fastfca_ctx *c, int threads, int bins_per_thread);
 

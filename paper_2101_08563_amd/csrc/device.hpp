@@ -62,6 +62,30 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Single precision reciprocal (v_rcp_f32, about 1 ulp).
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Natural log in single precision from the hardware log2 (v_log_f32) for
+// normal positive inputs; used only for the per-iteration likelihood trace.
+__device__ __forceinline__ float ln_fast(float x) {
+    return __builtin_amdgcn_logf(x) * 0.69314718055994531f;
+}
+
+// Double precision 1/x and 1/sqrt(x) from the hardware estimates refined by
+// Newton steps (each step squares the relative error; two steps reach full
+// double precision from the estimate). For finite, normal, positive x.
+__device__ __forceinline__ double rcp_d(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ double rsqrt_d(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    // y <- y (3 - x y^2) / 2
+    y = y * fma(-0.5 * x, y * y, 1.5);
+    y = y * fma(-0.5 * x, y * y, 1.5);
+    return y;
+}
+
 // ----------------------------------------------------------------- complex fp64
 struct cd {
     double re, im;

@@ -36,8 +36,10 @@ constexpr int kRedW = kMaxM * kMaxM * kMaxM;  // widest reduction (all Q_m, M = 
 constexpr double kLnPi = 1.1447298858494002;  // ln(pi)
 
 struct EmSmem {
-    float red[2][kMaxWaves][kRedW];
-    double red_d[2][kMaxWaves];
+    // reduction partials, value-major with one slot per wave; slots of waves
+    // that do not exist stay zero so every sum runs over all 16 slots
+    alignas(16) float red[2][kRedW][kMaxWaves];
+    alignas(16) double red_d[2][kMaxWaves];
     double qtot[kRedW];
     double2 Pd[kMaxM * kMaxM];
     float2 P32[kMaxM * kMaxM];
@@ -170,10 +172,86 @@ __device__ __forceinline__ int ip_sweep_lds(EmSmem &sm, double &ldet) {
     return ST_OK;
 }
 
+// Fixed-order sum of the 16 wave slots of one reduced value.
+__device__ __forceinline__ float sum_slots(const float *p) {
+    const float4 a = *reinterpret_cast<const float4 *>(p);
+    const float4 b = *reinterpret_cast<const float4 *>(p + 4);
+    const float4 c = *reinterpret_cast<const float4 *>(p + 8);
+    const float4 d = *reinterpret_cast<const float4 *>(p + 12);
+    return (((a.x + a.y) + (a.z + a.w)) + ((b.x + b.y) + (b.z + b.w))) +
+           (((c.x + c.y) + (c.z + c.w)) + ((d.x + d.y) + (d.z + d.w)));
+}
+__device__ __forceinline__ double sum_slots(const double *p) {
+    double s[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s[i] = p[2 * i] + p[2 * i + 1];
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
 // Real parameters of a Hermitian M x M matrix: M diagonal entries, then
 // (re, im) of each upper-triangle entry (r < c) in row-major order.
 template <int M>
 __device__ __forceinline__ constexpr int herm_n() { return M * M; }
+
+// IP sweep for M = 2 in registers (every lane of wave 0 computes the same
+// values): the 2 x 2 system of eq:ip1 is solved by its adjugate (Cramer's
+// rule), which for a 2 x 2 matrix is the elimination result without row
+// exchanges; the pivot test compares |det| with the largest entry squared.
+// qsum: the 8 reduced Hermitian parameters (Q_1 then Q_2), already / T.
+__device__ __forceinline__ int ip_sweep_reg2(EmSmem &sm, const double (&q)[8], double &ldet) {
+    cd P[2][2];
+    P[0][0] = ld(sm.Pd[0]);
+    P[0][1] = ld(sm.Pd[1]);
+    P[1][0] = ld(sm.Pd[2]);
+    P[1][1] = ld(sm.Pd[3]);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const double q00 = q[4 * m + 0], q11 = q[4 * m + 1];
+        const cd q01 = cmk(q[4 * m + 2], q[4 * m + 3]);
+        if (!(fabs(q00) < INFINITY) || !(fabs(q11) < INFINITY) || !(abs2(q01) < INFINITY))
+            return ST_NONFINITE;
+        // A = P^H Q
+        cd A[2][2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const cd p0 = conjd(P[0][r]), p1 = conjd(P[1][r]);
+            A[r][0] = q00 * p0 + p1 * conjd(q01);
+            A[r][1] = p0 * q01 + q11 * p1;
+        }
+        const cd det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+        const double d2 = abs2(det);
+        const double amax2 = fmax(fmax(abs2(A[0][0]), abs2(A[0][1])), fmax(abs2(A[1][0]), abs2(A[1][1])));
+        if (!(amax2 > 0.0) || !(amax2 < INFINITY) || !(d2 >= kPivotTol * kPivotTol * amax2 * amax2))
+            return ST_SINGULAR;
+        // w = adj(A) e_m / det, with 1/det = conj(det) / |det|^2
+        const cd idet = rcp_d(d2) * conjd(det);
+        cd w0, w1;
+        if (m == 0) {
+            w0 = A[1][1] * idet;
+            w1 = cmk(-A[1][0].re, -A[1][0].im) * idet;
+        } else {
+            w0 = cmk(-A[0][1].re, -A[0][1].im) * idet;
+            w1 = A[0][0] * idet;
+        }
+        // normalization so that w^H Q w = 1
+        const double qq = q00 * abs2(w0) + q11 * abs2(w1) + 2.0 * (conjd(w0) * q01 * w1).re;
+        if (!(qq > 0.0) || !(qq < INFINITY)) return ST_SINGULAR;
+        const double inv = rsqrt_d(qq);
+        P[0][m] = inv * w0;
+        P[1][m] = inv * w1;
+    }
+    // ln|det P|^2 for the likelihood trace (single precision logarithm)
+    ldet = static_cast<double>(ln_fast(static_cast<float>(abs2(P[0][0] * P[1][1] - P[0][1] * P[1][0]))));
+    sm.Pd[0] = st(P[0][0]);
+    sm.Pd[1] = st(P[0][1]);
+    sm.Pd[2] = st(P[1][0]);
+    sm.Pd[3] = st(P[1][1]);
+    sm.P32[0] = make_float2(static_cast<float>(P[0][0].re), static_cast<float>(P[0][0].im));
+    sm.P32[1] = make_float2(static_cast<float>(P[0][1].re), static_cast<float>(P[0][1].im));
+    sm.P32[2] = make_float2(static_cast<float>(P[1][0].re), static_cast<float>(P[1][0].im));
+    sm.P32[3] = make_float2(static_cast<float>(P[1][1].re), static_cast<float>(P[1][1].im));
+    return ST_OK;
+}
 
 template <int M, int N, int BPT>
 __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, EmSmem &sm) {
@@ -182,7 +260,6 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, EmSmem &
     const int nthr = blockDim.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
-    const int nw = nthr >> 6;
     const int T = it.T;
     const float invTf = 1.0f / static_cast<float>(T);
     const double invT = 1.0 / static_cast<double>(T);
@@ -212,6 +289,8 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, EmSmem &
         sm.Pd[tid] = it.P[tid];
     }
     if (tid == 0) sm.flag = ST_OK;
+    for (int i = tid; i < 2 * kRedW * kMaxWaves; i += nthr) (&sm.red[0][0][0])[i] = 0.0f;
+    if (tid < 2 * kMaxWaves) (&sm.red_d[0][0])[tid] = 0.0;
     __syncthreads();
 
     double ldet_prev = 0.0;  // ln|det P|^2 of the iterate being evaluated (wave 0)
@@ -240,7 +319,7 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, EmSmem &
             if (iter > 0 && valid[k]) {
                 float acc = 0.0f;
 #pragma unroll
-                for (int m = 0; m < M; ++m) acc += __logf(s2[m]) + U[k][m] * w[m];
+                for (int m = 0; m < M; ++m) acc += ln_fast(s2[m]) + U[k][m] * w[m];
                 llp += static_cast<double>(acc);
             }
             if (!last) {
@@ -275,30 +354,35 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, EmSmem &
         if (lane == 0) {
             if (!last) {
 #pragma unroll
-                for (int i = 0; i < NQ; ++i) sm.red[buf][wid][i] = q[i];
+                for (int i = 0; i < NQ; ++i) sm.red[buf][i][wid] = q[i];
             }
             sm.red_d[buf][wid] = llp;
         }
         __syncthreads();
         if (wid == 0) {
             if (iter > 0) {
-                double s = 0.0;
-                for (int w = 0; w < nw; ++w) s += sm.red_d[buf][w];
+                const double s = sum_slots(sm.red_d[buf]);
                 const double ll = ldet_prev - static_cast<double>(M) * kLnPi - s * invT;
                 if (lane == 0) it.ll_trace[iter - 1] = ll;
                 if (!(ll == ll) || ll == INFINITY || ll == -INFINITY) status = ST_NONFINITE;
             }
             if (!last && status == ST_OK) {
-                if (lane < NQ) {
-                    float s = 0.0f;
-                    for (int w = 0; w < nw; ++w) s += sm.red[buf][w][lane];
-                    sm.qtot[lane] = static_cast<double>(s) * invT;
-                }
-                __threadfence_block();
-                __builtin_amdgcn_wave_barrier();
-                // ------------- IP sweep in double precision (LDS-resident matrices)
                 double ldet = 0.0;
-                status = ip_sweep_lds<M>(sm, ldet);
+                if constexpr (M == 2) {
+                    // lane i sums value i over the wave slots, then every lane
+                    // reads all eight sums from registers
+                    double qs[8];
+                    const float mine = lane < 8 ? sum_slots(sm.red[buf][lane]) : 0.0f;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) qs[i] = static_cast<double>(readlane_f(mine, i)) * invT;
+                    status = ip_sweep_reg2(sm, qs, ldet);
+                } else {
+                    if (lane < NQ) sm.qtot[lane] = static_cast<double>(sum_slots(sm.red[buf][lane])) * invT;
+                    __threadfence_block();
+                    __builtin_amdgcn_wave_barrier();
+                    // IP sweep in double precision (LDS-resident matrices)
+                    status = ip_sweep_lds<M>(sm, ldet);
+                }
                 if (status == ST_OK) ldet_prev = ldet;
             }
             if (lane == 0) sm.flag = status;
@@ -359,16 +443,15 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, EmSmem &
             for (int m = 0; m < M; ++m) part[m] = wave_sum(part[m]);
             if (lane == 0) {
 #pragma unroll
-                for (int m = 0; m < M; ++m) sm.red[buf][wid][m] = part[m];
+                for (int m = 0; m < M; ++m) sm.red[buf][m][wid] = part[m];
             }
             __syncthreads();
             float rl[M];
             bool good = true;
+            const float mine = lane < M ? sum_slots(sm.red[buf][lane]) : 0.0f;
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                float s = 0.0f;
-                for (int w = 0; w < nw; ++w) s += sm.red[buf][w][m];
-                const float l = s * invTf;
+                const float l = readlane_f(mine, m) * invTf;
                 good = good && (l > 0.0f) && (l < INFINITY);
                 lam[n][m] = l;
                 rl[m] = rcp(l);

@@ -24,6 +24,7 @@ struct BptTable {
             case 2: return em_kernel<M, N, 2>;
             case 4: return em_kernel<M, N, 4>;
             case 8: return em_kernel<M, N, 8>;
+            case 16: return em_kernel<M, N, 16>;
             default: return nullptr;
         }
     }

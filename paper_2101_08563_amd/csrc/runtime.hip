@@ -557,6 +557,19 @@ int fastfca_get_params(fastfca_ctx *c, int b, fastfca_c128 *P, float *lambda, fl
     return FASTFCA_OK;
 }
 
+int fastfca_set_params(fastfca_ctx *c, int b, const fastfca_c128 *P, const float *lambda,
+                       const float *v) {
+    if (!valid_problem(c, b)) return c ? set_err(c, FASTFCA_E_ARG, "bad mixture index %d", b) : FASTFCA_E_ARG;
+    auto &p = c->probs[b];
+    const size_t F = p.F, T = p.T, M = p.M, N = p.N;
+    if (P) HIPCHK(c, hipMemcpyAsync(p.P, P, sizeof(double2) * F * M * M, hipMemcpyDeviceToDevice, c->stream));
+    if (lambda)
+        HIPCHK(c, hipMemcpyAsync(p.lam, lambda, sizeof(float) * F * N * M, hipMemcpyDeviceToDevice, c->stream));
+    if (v) HIPCHK(c, hipMemcpyAsync(p.v, v, sizeof(float) * F * T * N, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, launch_fill_int(c->d_status + p.item0, p.F, ST_OK, c->stream));
+    return FASTFCA_OK;
+}
+
 int fastfca_shape(const fastfca_ctx *c, int b, int *F, int *T, int *M, int *N) {
     if (!c || b < 0 || b >= static_cast<int>(c->probs.size())) return FASTFCA_E_ARG;
     const auto &p = c->probs[b];
@@ -577,7 +590,8 @@ int fastfca_set_config(fastfca_ctx *c, int threads, int bins_per_thread) {
         return FASTFCA_OK;
     }
     if (threads < 64 || (threads & 63) || threads * bins_per_thread > kResidentBins ||
-        (bins_per_thread != 2 && bins_per_thread != 4 && bins_per_thread != 8))
+        (bins_per_thread != 2 && bins_per_thread != 4 && bins_per_thread != 8 &&
+         bins_per_thread != 16))
         return set_err(c, FASTFCA_E_ARG, "invalid config threads=%d bins_per_thread=%d", threads,
                        bins_per_thread);
     for (auto &cc : c->classes)
@@ -723,7 +737,7 @@ int fastfca_autotune(fastfca_ctx *c, int n_iter, const char *cache_path) {
         for (auto &cc : c->classes) {
             int bt = cc.threads, bb = cc.bpt;
             float best = 1e30f;
-            for (int bpt : {2, 4, 8}) {
+            for (int bpt : {2, 4, 8, 16}) {
                 const int th = threads_for(cc.Tmax, bpt);
                 if (!th || !em_supported(cc.M, cc.N, bpt)) continue;
                 cc.threads = th;

@@ -32,6 +32,7 @@ SIGNATURES = {
     "fastfca_ll_trace": (_i, [_vp, _i, ctypes.POINTER(_d), _i]),
     "fastfca_mwf": (_i, [_vp, _i, _vp]),
     "fastfca_get_params": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "fastfca_set_params": (_i, [_vp, _i, _vp, _vp, _vp]),
     "fastfca_shape": (_i, [_vp, _i, _pi, _pi, _pi, _pi]),
     "fastfca_num_problems": (_i, [_vp]),
     "fastfca_set_config": (_i, [_vp, _i, _i]),
@@ -187,6 +188,14 @@ class FastFCA:
         v = torch.empty((F, T, N), dtype=torch.float32, device="cuda")
         self._chk(self._lib.fastfca_get_params(self._ctx, b, _ptr(P), _ptr(lam), _ptr(v)))
         return P, lam, v
+
+    def set_params(self, P=None, lam=None, v=None, b=0):
+        """Overwrite (P, lambda, v) of mixture b from CUDA tensors (None keeps)."""
+        F, T, M, N = self.shape(b)
+        _check_dev(P, torch.complex128, (F, M, M), "P")
+        _check_dev(lam, torch.float32, (F, N, M), "lam")
+        _check_dev(v, torch.float32, (F, T, N), "v")
+        self._chk(self._lib.fastfca_set_params(self._ctx, b, _ptr(P), _ptr(lam), _ptr(v)))
 
     def set_config(self, threads=0, bins_per_thread=0):
         self._chk(self._lib.fastfca_set_config(self._ctx, int(threads), int(bins_per_thread)))
