@@ -47,6 +47,32 @@ def em_bytes_per_bin(M: int, N: int) -> int:
     return 8 * M + 8 * N
 
 
+KERNEL_FILES = ["em_item.hpp", "em_kernel.hip", "device.hpp", "internal.hpp"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_FILES:
+        with open(os.path.join(ROOT, "paper_2101_08563_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per em_kernel launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when
+    the kernel sources have changed since the counters were taken."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "em_kernel_c1_traffic.json")) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,7 +170,7 @@ def main():
             "peak": FP32_FMA_PEAK / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_FMA_PEAK,
-            "traffic": None,
+            "traffic": measured_traffic() if iters == 100 else None,
             "em_ms_per_launch": em_ms,
             "flops_per_launch": flops,
             "hbm_algorithmic_bytes_per_launch": hbm_bytes,
