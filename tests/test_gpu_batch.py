@@ -1,0 +1,133 @@
+"""Batched FastFCA: many mixtures of mixed (M, N, T) in one persistent launch
+per em_step call, against the FP64 oracle and against single-mixture runs."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2101_08563_amd import FastFCA, synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+
+
+def batch_inputs(n_mix=8, F=12, seed=0):
+    specs = synth.batch_specs(B=n_mix, F=F, seed=seed)
+    out = []
+    for s in specs:
+        x = synth.mixture(F=s["F"], T=s["T"], M=s["M"], N=s["N"], rank=s["rank"], diffuse=s["diffuse"],
+                          config_id=s["config_id"], mixture_id=s["mixture_id"])
+        P0, lam0, v0 = synth.init_params(x, s["N"], config_id=s["config_id"], mixture_id=s["mixture_id"])
+        out.append((x, P0, lam0, v0, s["N"]))
+    return out
+
+
+def make_batch(inputs):
+    probs = []
+    for x, P0, lam0, v0, N in inputs:
+        probs.append(dict(x=torch.from_numpy(x).to(DEV), N=N, P0=torch.from_numpy(P0).to(DEV),
+                          lam0=torch.from_numpy(lam0).to(DEV), v0=torch.from_numpy(v0).to(DEV)))
+    return FastFCA.from_batch(probs), probs
+
+
+def test_batch_shapes_cover_the_classes():
+    specs = synth.batch_specs(B=256, F=513)
+    Ms = {s["M"] for s in specs}
+    assert Ms == {2, 3, 4}
+    assert all(s["N"] - s["M"] in (1, 2) for s in specs)
+    Ts = [s["T"] for s in specs]
+    assert 200 <= min(Ts) and max(Ts) <= 2000
+
+
+def test_batch_matches_oracle_per_mixture():
+    inputs = batch_inputs(8, F=12)
+    ctx, _ = make_batch(inputs)
+    assert ctx.num_problems == 8
+    ctx.em_step(20)
+    ctx.sync()
+    for b, (x, P0, lam0, v0, N) in enumerate(inputs):
+        P, lam, v = (t.cpu().numpy() for t in ctx.get_params(b))
+        Po, lo, vo, tro = oracle.fit(x, P0, lam0, v0, 20, trace=True)
+        llo, _ = oracle.loglik(x, Po, lo, vo)
+        errs = dict(v=rel(v, vo), lam=rel(lam, lo), P=rel(P, Po), ll=abs(ctx.loglik(b) - llo))
+        print("mixture", b, x.shape, N, errs, flush=True)
+        assert errs["v"] < 1e-4 and errs["lam"] < 1e-4 and errs["P"] < 1e-4 and errs["ll"] < 1e-6, errs
+        tr = ctx.ll_trace(b)
+        assert np.abs(tr - tro).max() < 1e-4
+        y = ctx.mwf(b).cpu().numpy()
+        yo = oracle.mwf(x, Po, lo, vo)
+        assert max(rel(y[n], yo[n]) for n in range(N)) < 1e-4
+    ctx.close()
+
+
+def test_batch_equals_single_runs():
+    """Each mixture of the batch ends where it ends when run alone (same
+    iterations; launch shapes differ, so equal up to single precision)."""
+    inputs = batch_inputs(5, F=6, seed=3)
+    ctx, _ = make_batch(inputs)
+    ctx.em_step(10)
+    ctx.sync()
+    for b, (x, P0, lam0, v0, N) in enumerate(inputs):
+        single = FastFCA(*(torch.from_numpy(a).to(DEV) for a in (x,)), N,
+                         *(torch.from_numpy(a).to(DEV) for a in (P0, lam0, v0)))
+        single.em_step(10)
+        Ps, ls, vs = (t.cpu().numpy() for t in single.get_params())
+        Pb, lb, vb = (t.cpu().numpy() for t in ctx.get_params(b))
+        single.close()
+        assert rel(vb, vs) < 2e-5 and rel(lb, ls) < 2e-5 and rel(Pb, Ps) < 2e-5
+    ctx.close()
+
+
+def test_batch_graph_replay_and_determinism():
+    """Replaying the captured graph (two calls of 5) equals one call of 10,
+    bitwise, and two identical batches give identical results."""
+    inputs = batch_inputs(4, F=5, seed=5)
+    a, _ = make_batch(inputs)
+    b, _ = make_batch(inputs)
+    a.em_step(5)
+    a.em_step(5)
+    b.em_step(10)
+    for k in range(4):
+        for ta, tb in zip(a.get_params(k), b.get_params(k)):
+            assert torch.equal(ta, tb)
+    a.close()
+    b.close()
+
+
+def test_batch_autotune_keeps_state_and_results():
+    inputs = batch_inputs(3, F=4, seed=7)
+    ctx, _ = make_batch(inputs)
+    before = [tuple(t.clone() for t in ctx.get_params(k)) for k in range(3)]
+    ctx.autotune(n_iter=3)
+    after = [ctx.get_params(k) for k in range(3)]
+    for bp, ap in zip(before, after):
+        for tb, ta in zip(bp, ap):
+            assert torch.equal(tb, ta)
+    ctx.em_step(8)
+    for k, (x, P0, lam0, v0, N) in enumerate(inputs):
+        Po, lo, vo, _ = oracle.fit(x, P0, lam0, v0, 8)
+        assert rel(ctx.get_params(k)[2].cpu().numpy(), vo) < 1e-4
+    ctx.close()
+
+
+def test_single_autotune_cache(tmp_path):
+    x = synth.mixture(F=8, T=700, M=2, N=3, config_id=40)
+    P0, lam0, v0 = synth.init_params(x, 3, config_id=40)
+    ctx = FastFCA(*(torch.from_numpy(a).to(DEV) for a in (x,)), 3,
+                  *(torch.from_numpy(a).to(DEV) for a in (P0, lam0, v0)))
+    cache = tmp_path / "tune.jsonl"
+    ctx.autotune(n_iter=4, cache_path=str(cache))
+    import json
+    lines = [json.loads(l) for l in cache.read_text().splitlines()]
+    assert lines and lines[0]["M"] == 2 and lines[0]["N"] == 3
+    th, bpt = ctx.get_config()
+    assert th * bpt >= 700
+    ctx.em_step(6)
+    Po, lo, vo, _ = oracle.fit(x, P0, lam0, v0, 6)
+    assert rel(ctx.get_params()[2].cpu().numpy(), vo) < 1e-4
+    ctx.close()
