@@ -63,10 +63,12 @@ enum {
 };
 
 /* Shape limits of the compiled kernels: 2 <= M <= FASTFCA_MAX_M,
- * 2 <= N <= FASTFCA_MAX_N, M <= T <= FASTFCA_MAX_T. */
+ * 2 <= N <= FASTFCA_MAX_N, M <= T <= FASTFCA_MAX_T. Shapes with M <= 4,
+ * N <= 8, T <= 2048 run with the whole frequency resident on chip; the rest
+ * re-read x from device memory each iteration. */
 #define FASTFCA_MAX_M 8
 #define FASTFCA_MAX_N 12
-#define FASTFCA_MAX_T 16384
+#define FASTFCA_MAX_T 4096
 
 /* One mixture of a batch (fastfca_init_batch). Pointer fields are device
  * pointers with the layouts above; P0/lambda0/v0 may be NULL (see init). */
@@ -177,7 +179,8 @@ int fastfca_num_problems(const fastfca_ctx *c);
  * subsequent fastfca_em_step: threads per workgroup (64..1024, multiple of
  * 64, or 0 = default) and bins per thread (2, 4, 8 or 16; 0 = default).
  * threads * bins_per_thread must cover the longest T of every (M,N) class and
- * may not exceed 2048; E_ARG otherwise.
+ * may not exceed 2048 (4096 with 4 or 8 bins per thread for classes outside
+ * the resident limits); E_ARG otherwise.
  */
 int fastfca_set_config(fastfca_ctx *c, int threads, int bins_per_thread);
 

@@ -9,7 +9,10 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfastfca.so")
-SOURCES = ["em_kernel.hip", "aux_kernels.hip", "runtime.hip"]
+# (source, extra defines, object name); the wide family is compiled once per M
+SOURCES = [("em_kernel.hip", [], "em_kernel.o"), ("aux_kernels.hip", [], "aux_kernels.o"),
+           ("runtime.hip", [], "runtime.o")] + [
+    ("em_wide_kernel.hip", ["-DFFCA_WIDE_M=%d" % m], "em_wide_m%d.o" % m) for m in range(2, 9)]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
@@ -27,11 +30,11 @@ def build(verbose: bool = True, jobs: int = 0) -> str:
     t0 = time.time()
     procs = []
     objs = []
-    for src in SOURCES:
-        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+    for src, defs, oname in SOURCES:
+        obj = os.path.join(objdir, oname)
         objs.append(obj)
-        cmd = [hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+        cmd = [hipcc, *HIPCC_FLAGS, *defs, "-c", os.path.join(CSRC, src), "-o", obj]
+        procs.append((oname, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     failed = []
     for src, p in procs:
         out, _ = p.communicate()

@@ -102,6 +102,39 @@ hipError_t launch_em_persistent(const EmLaunch &a, int threads, int bpt, int gri
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ wide family
+template <> void (*wide_lookup<2>(int, int))(EmLaunch);
+template <> void (*wide_lookup<3>(int, int))(EmLaunch);
+template <> void (*wide_lookup<4>(int, int))(EmLaunch);
+template <> void (*wide_lookup<5>(int, int))(EmLaunch);
+template <> void (*wide_lookup<6>(int, int))(EmLaunch);
+template <> void (*wide_lookup<7>(int, int))(EmLaunch);
+template <> void (*wide_lookup<8>(int, int))(EmLaunch);
+
+static EmFn wide_fn(int M, int N, int bpt) {
+    switch (M) {
+        case 2: return wide_lookup<2>(N, bpt);
+        case 3: return wide_lookup<3>(N, bpt);
+        case 4: return wide_lookup<4>(N, bpt);
+        case 5: return wide_lookup<5>(N, bpt);
+        case 6: return wide_lookup<6>(N, bpt);
+        case 7: return wide_lookup<7>(N, bpt);
+        case 8: return wide_lookup<8>(N, bpt);
+        default: return nullptr;
+    }
+}
+
+bool em_wide_supported(int M, int N, int bpt) { return wide_fn(M, N, bpt) != nullptr; }
+
+hipError_t launch_em_wide(int M, int N, int bpt, int threads, const EmLaunch &a, int grid,
+                          hipStream_t s) {
+    EmFn fn = wide_fn(M, N, bpt);
+    if (!fn) return hipErrorInvalidValue;
+    if (threads < 64 || (threads & 63) || threads * bpt > kWideMaxT) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(threads), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_em(int M, int N, int bpt, int threads, const EmLaunch &a, int grid,
                      hipStream_t s) {
     EmFn fn = em_lookup(M, N, bpt);

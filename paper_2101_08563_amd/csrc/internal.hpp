@@ -44,6 +44,16 @@ hipError_t launch_em(int M, int N, int bpt, int threads, const EmLaunch &a, int 
                      hipStream_t s);
 bool em_supported(int M, int N, int bpt);
 
+// Wide family (M <= 8, N <= 12, T <= kWideBins = 4096): x is re-read from
+// global memory each iteration; see em_wide.hpp. One lookup per M, defined in
+// the per-M translation units of em_wide_kernel.hip.
+template <int M>
+void (*wide_lookup(int N, int bpt))(EmLaunch);
+hipError_t launch_em_wide(int M, int N, int bpt, int threads, const EmLaunch &a, int grid,
+                          hipStream_t s);
+bool em_wide_supported(int M, int N, int bpt);
+constexpr int kWideMaxT = 4096;
+
 // Persistent launch over a mixed list of work items (any supported (M, N) in
 // the batch class table), pulling items from a device counter.
 hipError_t launch_em_persistent(const EmLaunch &a, int threads, int bpt, int grid,

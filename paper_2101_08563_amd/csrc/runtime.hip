@@ -46,6 +46,7 @@ struct Problem {
 
 struct ClassCfg {
     int M, N, Tmax;
+    bool wide = false;  // wide family (x re-read per iteration) instead of resident
     int threads = 0, bpt = 0;
     std::vector<int> items;  // item indices of this class, in launch order
 };
@@ -131,11 +132,11 @@ void drop_graph(fastfca_ctx *c) {
 }
 
 // Smallest workgroup (multiple of 64) holding T bins at bpt bins per thread,
-// or 0 if it exceeds the kernel's thread limit 2048 / bpt.
-int threads_for(int T, int bpt) {
+// or 0 if it exceeds the family's limit (threads * bpt <= cap).
+int threads_for(int T, int bpt, int cap = kResidentBins) {
     int th = ((T + bpt - 1) / bpt + 63) / 64 * 64;
     if (th < 64) th = 64;
-    return th * bpt <= kResidentBins ? th : 0;
+    return th * bpt <= cap ? th : 0;
 }
 
 bool pick_default(int Tmax, int &threads, int &bpt) {
@@ -150,6 +151,22 @@ bool pick_default(int Tmax, int &threads, int &bpt) {
     }
     return false;
 }
+
+// Kernel family of an (M, N, Tmax) class: resident when its bins fit on chip
+// next to x, wide otherwise.
+bool use_resident(int M, int N, int Tmax) {
+    return M <= 4 && N <= 8 && Tmax <= kResidentBins && em_supported(M, N, 4);
+}
+
+// Default launch shape of a class.
+bool pick_class(ClassCfg &cc) {
+    cc.wide = !use_resident(cc.M, cc.N, cc.Tmax);
+    if (!cc.wide) return pick_default(cc.Tmax, cc.threads, cc.bpt);
+    cc.bpt = 8;
+    cc.threads = threads_for(cc.Tmax, 8, kWideMaxT);
+    return cc.threads != 0 && em_wide_supported(cc.M, cc.N, 8);
+}
+
 
 int validate_shape(fastfca_ctx *c, int F, int T, int M, int N) {
     if (F < 1 || T < 1 || M < 2 || N < 2)
@@ -210,10 +227,9 @@ int build_items(fastfca_ctx *c) {
             return c->h_items[a].T > c->h_items[b].T;
         });
     for (auto &cc : c->classes) {
-        if (!pick_default(cc.Tmax, cc.threads, cc.bpt))
-            return set_err(c, FASTFCA_E_UNSUPPORTED, "T=%d too long for the resident kernels", cc.Tmax);
-        if (!em_supported(cc.M, cc.N, cc.bpt))
-            return set_err(c, FASTFCA_E_UNSUPPORTED, "no compiled kernel for M=%d N=%d", cc.M, cc.N);
+        if (!pick_class(cc))
+            return set_err(c, FASTFCA_E_UNSUPPORTED, "no compiled kernel for M=%d N=%d T=%d", cc.M,
+                           cc.N, cc.Tmax);
     }
     int rc;
     if ((rc = dalloc(c, &c->d_status, total)) != FASTFCA_OK) return rc;
@@ -370,7 +386,7 @@ int create(fastfca_ctx **out, int B, const fastfca_problem *probs, uint64_t seed
             bool ok = true;
             for (auto &cc : c->classes) {
                 Tmax = std::max(Tmax, cc.Tmax);
-                ok = ok && persistent_supported(cc.M, cc.N);
+                ok = ok && !cc.wide && persistent_supported(cc.M, cc.N);
             }
             if (!ok || !pick_default(Tmax, c->p_threads, c->p_bpt)) c->persistent = false;
             if (c->persistent && c->p_bpt == 2) c->p_bpt = 4;
@@ -406,8 +422,12 @@ int record_em(fastfca_ctx *c, int n_iter) {
         const auto &cc = c->classes[k];
         EmLaunch a{c->d_items + c->class_first[k], static_cast<int>(cc.items.size()), n_iter,
                    nullptr};
-        HIPCHK(c, launch_em(cc.M, cc.N, cc.bpt, cc.threads, a, static_cast<int>(cc.items.size()),
-                            c->stream));
+        if (cc.wide)
+            HIPCHK(c, launch_em_wide(cc.M, cc.N, cc.bpt, cc.threads, a,
+                                     static_cast<int>(cc.items.size()), c->stream));
+        else
+            HIPCHK(c, launch_em(cc.M, cc.N, cc.bpt, cc.threads, a, static_cast<int>(cc.items.size()),
+                                c->stream));
     }
     return FASTFCA_OK;
 }
@@ -585,19 +605,27 @@ int fastfca_num_problems(const fastfca_ctx *c) { return c ? static_cast<int>(c->
 int fastfca_set_config(fastfca_ctx *c, int threads, int bins_per_thread) {
     if (!c) return FASTFCA_E_ARG;
     if (threads == 0 && bins_per_thread == 0) {
-        for (auto &cc : c->classes) pick_default(cc.Tmax, cc.threads, cc.bpt);
+        for (auto &cc : c->classes) pick_class(cc);
         drop_graph(c);
         return FASTFCA_OK;
     }
-    if (threads < 64 || (threads & 63) || threads * bins_per_thread > kResidentBins ||
+    if (threads < 64 || (threads & 63) || threads * bins_per_thread > kWideMaxT ||
         (bins_per_thread != 2 && bins_per_thread != 4 && bins_per_thread != 8 &&
          bins_per_thread != 16))
         return set_err(c, FASTFCA_E_ARG, "invalid config threads=%d bins_per_thread=%d", threads,
                        bins_per_thread);
-    for (auto &cc : c->classes)
+    for (auto &cc : c->classes) {
         if (threads * bins_per_thread < cc.Tmax)
             return set_err(c, FASTFCA_E_ARG, "threads*bins_per_thread=%d < T=%d",
                            threads * bins_per_thread, cc.Tmax);
+        if (!cc.wide && threads * bins_per_thread > kResidentBins)
+            return set_err(c, FASTFCA_E_ARG, "threads*bins_per_thread=%d > 2048 for M=%d N=%d",
+                           threads * bins_per_thread, cc.M, cc.N);
+        if (cc.wide && (threads * bins_per_thread > kWideMaxT ||
+                        !em_wide_supported(cc.M, cc.N, bins_per_thread)))
+            return set_err(c, FASTFCA_E_ARG, "M=%d N=%d T=%d: the wide kernels take 4 or 8 bins per "
+                           "thread and at most 4096 bins", cc.M, cc.N, cc.Tmax);
+    }
     if (c->persistent) {
         c->p_threads = threads;
         c->p_bpt = bins_per_thread;
@@ -738,8 +766,10 @@ int fastfca_autotune(fastfca_ctx *c, int n_iter, const char *cache_path) {
             int bt = cc.threads, bb = cc.bpt;
             float best = 1e30f;
             for (int bpt : {2, 4, 8, 16}) {
-                const int th = threads_for(cc.Tmax, bpt);
-                if (!th || !em_supported(cc.M, cc.N, bpt)) continue;
+                const int th = threads_for(cc.Tmax, bpt, cc.wide ? kWideMaxT : kResidentBins);
+                if (!th) continue;
+                if (cc.wide ? !em_wide_supported(cc.M, cc.N, bpt) : !em_supported(cc.M, cc.N, bpt))
+                    continue;
                 cc.threads = th;
                 cc.bpt = bpt;
                 float ms;
