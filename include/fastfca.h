@@ -196,11 +196,123 @@ int fastfca_autotune(fastfca_ctx *c, int n_iter, const char *cache_path);
 /* Launch configuration in effect for the (M,N) class of mixture b. */
 int fastfca_get_config(const fastfca_ctx *c, int b, int *threads, int *bins_per_thread);
 
+/*
+ * fastfca_synth_mixture -- draw a seeded synthetic mixture x [F][T][M]
+ * (device, complex64, caller-allocated) from the FCA generative model of
+ * Sec. III-A: c_n ~ N_c(0, v_n R_n), x = sum_n c_n (eq:summodel), with
+ * v_n = W_n H_n of rank `rank` (Exp(1) factors) and R_n(f) = a a^H +
+ * diffuse I, a_m = exp(i theta) with theta uniform. Counter-based
+ * (SplitMix64) so any mixture is reproducible from (seed, shape). A data
+ * utility for benchmarks and training sets, not part of the method.
+ * Allocates and frees a small workspace; synchronizes the stream.
+ * Limits: 1 <= M <= 8, N >= 1, rank >= 1.
+ */
+int fastfca_synth_mixture(fastfca_c64 *x, int F, int T, int M, int N, int rank, float diffuse,
+                          uint64_t seed, void *hip_stream);
+
 /* Text of the last error of c (or of the last failed init when c is NULL). */
 const char *fastfca_last_error(const fastfca_ctx *c);
 
 /* Release every device buffer of c. c may be NULL. */
 void fastfca_destroy(fastfca_ctx *c);
+
+/* ====================================================================
+ * Learned warm start (not in the paper; the paper lists initialization
+ * robustness and convergence acceleration as future work, Sec. VIII).
+ * A 1-D convolutional network over time, applied to every frequency with
+ * shared weights, maps whitened log-powers to initial lambda and v; the
+ * IP+EM iteration then refines them. All pointers are device pointers; all
+ * calls are asynchronous on the given stream; they return FASTFCA_OK,
+ * FASTFCA_E_ARG (bad shape/argument) or FASTFCA_E_HIP, with text in
+ * fastfca_net_last_error().
+ *
+ * Tensors: activations float [S][C][T] (S sequences, i.e. frequencies,
+ * C <= 64 channels); a convolution with kernel size ks in {1, 5} and zero
+ * "same" padding uses weights float [Cout][Cin][ks] packed to bfloat16
+ * [Cout][Kp], Kp = Cin*ks rounded up to a multiple of 16 (<= 320), for the
+ * 16x16x16 bf16 MFMA with float accumulation.
+ * ==================================================================== */
+
+/* Text of the last error of the network entry points. */
+const char *fastfca_net_last_error(void);
+
+/* Pack float weights W (row co at W + co*ldw holding entries ci*ks + k,
+ * ldw >= Cin*ks) into the bf16 GEMM operand Wb[Cout][Kp], column order
+ * k-major: Wb[co][k*Cin + ci] = W[co][ci*ks + k]; with transpose_flip != 0
+ * into the operand of the data-gradient convolution, Wb[ci][k*Cout + co] =
+ * W[co][ci*ks + ks-1-k] (Kp >= Cout*ks, Cin rows). */
+int fastfca_net_pack_weights(const float *W, int ldw, int Cout, int Cin, int ks, int Kp, int transpose_flip,
+                             uint16_t *Wb, void *stream);
+
+/* Y[s][co][t] = epilogue(pre), pre = bias[co] + sum_{ci,k} W[co][ci][k] X[s][ci][t+k-ks/2]
+ * (X zero outside [0,T)); mode 0: Y = pre, 1: relu(pre), 2: Res + relu(pre),
+ * 3: Res + pre. bias may be NULL (zero); Pre (optional) receives pre.
+ * Res and Y are [S][Cout][T]; Y may alias Res. */
+int fastfca_net_conv_fwd(const float *X, int S, int Cin, int T, const uint16_t *Wb, int Kp, int ks,
+                         const float *bias, int Cout, float *Y, int mode, const float *Res, float *Pre,
+                         void *stream);
+
+/* Weight and bias gradients of the convolution, ACCUMULATED (+=) into float
+ * dW (row co at dW + co*Kp, entry ci*ks + k: the layout of the float master
+ * packed by fastfca_net_pack_weights with ldw = Kp) and db[Cout] (may be NULL):
+ * dW += sum_{s,t} G[s][co][t] X[s][ci][t+k-ks/2]. Float atomics: the
+ * summation order is not fixed. */
+int fastfca_net_conv_bwd_weight(const float *G, int S, int Cout, const float *X, int Cin, int T, int Kp,
+                                int ks, float *dW, float *db, void *stream);
+
+/* out[i] = G[i] if Pre[i] > 0 else 0, i < n. */
+int fastfca_net_relu_grad(const float *G, const float *Pre, float *out, uint64_t n, void *stream);
+
+/* pooled[i] = (1/T) sum_t H[i][t], i < SC (SC = S*C rows of length T). */
+int fastfca_net_mean_t(const float *H, int SC, int T, float *pooled, void *stream);
+
+/* dH[i][t] += dpooled[i] / T. */
+int fastfca_net_mean_t_bwd(const float *dpooled, int SC, int T, float *dH, void *stream);
+
+/* out[s][j] = bl[j] + sum_c Wl[j][c] in[s][c]. */
+int fastfca_net_linear_fwd(const float *in, int S, int C, const float *Wl, const float *bl, int J,
+                           float *out, void *stream);
+
+/* Gradients of linear_fwd: dWl[j][c] += sum_s g[s][j] in[s][c],
+ * dbl[j] += sum_s g[s][j], din[s][c] = sum_j Wl[j][c] g[s][j]. */
+int fastfca_net_linear_bwd(const float *in, int S, int C, const float *Wl, int J, const float *g,
+                           float *dWl, float *dbl, float *din, void *stream);
+
+/* Permutation-invariant loss per sequence s (N <= 4 sources):
+ *   loss[s] = min over orders pi of
+ *     mean_{n,t} (lv[s][pi(n)][t] - tv[s][n][t])^2 + wl * mean_{n,m} (ll[s][pi(n)][m] - tl[s][n][m])^2
+ * (orders enumerated lexicographically, first minimum kept); perm [S][N]
+ * (optional) receives pi; glv [S][N][T], gll [S][N][M] (optional) receive the
+ * gradient of loss[s] through the minimizing order. */
+int fastfca_net_pit_loss(const float *lv, const float *tv, const float *ll, const float *tl, int S, int N,
+                         int M, int T, float wl, float *loss, int *perm, float *glv, float *gll,
+                         void *stream);
+
+/* AdamW step (decoupled weight decay) on n parameters: m, v moments; the
+ * gradient is scaled by grad_scale first; step >= 1 sets the bias
+ * corrections 1 - beta^step. */
+int fastfca_net_adamw(float *p, const float *g, float *m, float *v, uint64_t n, float lr, float beta1,
+                      float beta2, float eps, float weight_decay, int step, float grad_scale, void *stream);
+
+/* Warm-start features of one mixture x [F][T][M] (M <= 4): per frequency
+ * C = (1/T) sum_t x_t x_t^H, P0 = C^{-1/2} (double precision, coupled
+ * Newton-Schulz) written to P0 [F][M][M], and
+ * feat[f][m][t] = ln(|(P0^H x_t)_m|^2 + eps) minus its mean over t. */
+int fastfca_ws_features(const fastfca_c64 *x, int F, int T, int M, float eps, fastfca_c128 *P0, float *feat,
+                        void *stream);
+
+/* Training targets from a fit (P, lambda, v) and the whitening P0 (M <= 4):
+ * each source is scaled so that tr R_n = M (R_n = P^{-H} diag(lambda_n) P^{-1},
+ * the trace normalization of the paper's SCM error, eq:Rerror); then
+ * tv[f][n][t] = ln(c_n v[f][t][n]) and tl[f][n][m] = ln [P0^H (R_n/c_n) P0]_{mm},
+ * c_n = tr R_n / M. */
+int fastfca_ws_targets(const fastfca_c128 *P, const float *lambda, const float *v, const fastfca_c128 *P0,
+                       int F, int T, int M, int N, float *tv, float *tl, void *stream);
+
+/* Network outputs to initial parameters: v[f][t][n] = exp(lv[f][n][t]),
+ * lambda[f][n][m] = exp(ll[f][n][m]) (arguments clamped to [-60, 60]). */
+int fastfca_ws_apply(const float *lv, const float *ll, int F, int T, int M, int N, float *v, float *lambda,
+                     void *stream);
 
 #ifdef __cplusplus
 }

@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfastfca.so")
 # (source, extra defines, object name); the wide family is compiled once per M
 SOURCES = [("em_kernel.hip", [], "em_kernel.o"), ("aux_kernels.hip", [], "aux_kernels.o"),
-           ("runtime.hip", [], "runtime.o")] + [
+           ("runtime.hip", [], "runtime.o"), ("synth_kernels.hip", [], "synth_kernels.o"),
+           ("net_kernels.hip", [], "net_kernels.o"), ("net_api.hip", [], "net_api.o")] + [
     ("em_wide_kernel.hip", ["-DFFCA_WIDE_M=%d" % m], "em_wide_m%d.o" % m) for m in range(2, 9)]
 
 HIPCC_FLAGS = [

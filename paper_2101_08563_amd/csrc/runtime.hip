@@ -23,6 +23,8 @@ hipError_t launch_loglik_terms(const WorkItem *items, int n_items, int M, const 
                                double *ll_f, hipStream_t s);
 hipError_t launch_mwf_bins(const WorkItem *items, const float2 *Bh, int F, int T, int M,
                            float2 *y, hipStream_t s);
+hipError_t launch_synth(float2 *x, int F, int T, int M, int N, int K, float delta, uint64_t seed,
+                        float *W, float2 *C, hipStream_t s);
 }  // namespace ffca
 
 using namespace ffca;
@@ -801,6 +803,24 @@ int fastfca_autotune(fastfca_ctx *c, int n_iter, const char *cache_path) {
     if (rc == FASTFCA_OK && e != hipSuccess)
         rc = set_err(c, FASTFCA_E_HIP, "autotune: %s", hipGetErrorString(e));
     return rc;
+}
+
+int fastfca_synth_mixture(fastfca_c64 *x, int F, int T, int M, int N, int rank, float diffuse,
+                          uint64_t seed, void *hip_stream) {
+    if (!x || F < 1 || T < 1 || M < 1 || M > 8 || N < 1 || rank < 1 || !(diffuse >= 0.0f))
+        return set_err(nullptr, FASTFCA_E_ARG, "synth: invalid arguments");
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    float *W = nullptr;
+    float2 *C = nullptr;
+    hipError_t e = hipMalloc(&W, sizeof(float) * static_cast<size_t>(N) * F * rank);
+    if (e == hipSuccess) e = hipMalloc(&C, sizeof(float2) * static_cast<size_t>(N) * F * M * M);
+    if (e == hipSuccess)
+        e = launch_synth(reinterpret_cast<float2 *>(x), F, T, M, N, rank, diffuse, seed, W, C, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(W);
+    hipFree(C);
+    if (e != hipSuccess) return set_err(nullptr, FASTFCA_E_HIP, "synth: %s", hipGetErrorString(e));
+    return FASTFCA_OK;
 }
 
 const char *fastfca_last_error(const fastfca_ctx *c) {

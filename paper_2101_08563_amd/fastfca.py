@@ -38,8 +38,25 @@ SIGNATURES = {
     "fastfca_set_config": (_i, [_vp, _i, _i]),
     "fastfca_autotune": (_i, [_vp, _i, ctypes.c_char_p]),
     "fastfca_get_config": (_i, [_vp, _i, _pi, _pi]),
+    "fastfca_synth_mixture": (_i, [_vp, _i, _i, _i, _i, _i, ctypes.c_float, _u64, _vp]),
     "fastfca_last_error": (ctypes.c_char_p, [_vp]),
     "fastfca_destroy": (None, [_vp]),
+    # learned warm start
+    "fastfca_net_last_error": (ctypes.c_char_p, []),
+    "fastfca_net_pack_weights": (_i, [_vp, _i, _i, _i, _i, _i, _i, _vp, _vp]),
+    "fastfca_net_conv_fwd": (_i, [_vp, _i, _i, _i, _vp, _i, _i, _vp, _i, _vp, _i, _vp, _vp, _vp]),
+    "fastfca_net_conv_bwd_weight": (_i, [_vp, _i, _i, _vp, _i, _i, _i, _i, _vp, _vp, _vp]),
+    "fastfca_net_relu_grad": (_i, [_vp, _vp, _vp, _u64, _vp]),
+    "fastfca_net_mean_t": (_i, [_vp, _i, _i, _vp, _vp]),
+    "fastfca_net_mean_t_bwd": (_i, [_vp, _i, _i, _vp, _vp]),
+    "fastfca_net_linear_fwd": (_i, [_vp, _i, _i, _vp, _vp, _i, _vp, _vp]),
+    "fastfca_net_linear_bwd": (_i, [_vp, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp]),
+    "fastfca_net_pit_loss": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, ctypes.c_float, _vp, _vp, _vp, _vp, _vp]),
+    "fastfca_net_adamw": (_i, [_vp, _vp, _vp, _vp, _u64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                               ctypes.c_float, ctypes.c_float, _i, ctypes.c_float, _vp]),
+    "fastfca_ws_features": (_i, [_vp, _i, _i, _i, ctypes.c_float, _vp, _vp, _vp]),
+    "fastfca_ws_targets": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _vp, _vp, _vp]),
+    "fastfca_ws_apply": (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _vp, _vp]),
 }
 
 
@@ -90,6 +107,17 @@ def _check_dev(t, dtype, shape, name):
         raise ValueError("%s must be a contiguous CUDA %s tensor of shape %s, got %s %s %s"
                          % (name, dtype, tuple(shape), t.device, t.dtype, tuple(t.shape)))
     return t
+
+
+def synth_mixture(F, T, M, N, rank=8, diffuse=0.05, seed=0, stream=None, out=None):
+    """Seeded synthetic mixture x [F,T,M] (CUDA complex64) drawn on the GPU."""
+    lib = load_library()
+    x = out if out is not None else torch.empty((F, T, M), dtype=torch.complex64, device="cuda")
+    _check_dev(x, torch.complex64, (F, T, M), "x")
+    rc = lib.fastfca_synth_mixture(_ptr(x), F, T, M, N, rank, float(diffuse), int(seed), _stream(stream))
+    if rc != OK:
+        raise FastFCAError(rc, lib.fastfca_last_error(None).decode())
+    return x
 
 
 class FastFCA:
