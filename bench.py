@@ -83,12 +83,21 @@ def main():
     ap.add_argument("--calib-copy", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--bpt", type=int, default=0)
+    ap.add_argument("--workload", choices=["headline", "batch", "large"], default="headline",
+                    help="headline: the contract line (M=2 N=3 F=513 T=1000); batch: 256 mixed "
+                         "mixtures in one persistent launch vs sequential runs; large: M=8 N=10 "
+                         "F=1025 T=4000")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build measures the single-GPU kernel "
               "(frequencies shard across GPUs with no exchange; see the design notes). "
               "--gpus %d is not supported." % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "large":
+        return bench_large(args)
 
     import torch
 
@@ -201,6 +210,102 @@ def main():
                       "frequencies, %.2f s" % (F, T, M, N, iters, t3 - t2),
         }
     ctx.close()
+    print(json.dumps(out))
+
+
+def _time(fn, stream, reps):
+    import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def bench_batch(args):
+    """256 mixtures with T ~ U{200..2000}, M in {2,3,4}, N in {M+1, M+2}, F=513,
+    drawn on the GPU; one persistent launch per em_step call, against the same
+    mixtures run one context at a time."""
+    import torch
+
+    from paper_2101_08563_amd import FastFCA, synth
+    from paper_2101_08563_amd.fastfca import synth_mixture
+
+    specs = synth.batch_specs(B=256, F=513)
+    iters = args.iters
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        xs = [synth_mixture(s["F"], s["T"], s["M"], s["N"], rank=8, diffuse=0.05, seed=2000 + i, stream=stream)
+              for i, s in enumerate(specs)]
+    stream.synchronize()
+    probs = [dict(x=x, N=s["N"]) for x, s in zip(xs, specs)]
+    batch = FastFCA.from_batch(probs, seed=1, stream=stream)
+    batch.em_step(2)
+    batch.sync()
+    t_batch = _time(lambda: batch.em_step(iters), stream, max(2, args.steps // 5))
+    batch.sync()
+    threads, bpt = batch.get_config()
+    batch.close()
+    singles = [FastFCA(x, s["N"], seed=1 + i, stream=stream) for i, (x, s) in enumerate(zip(xs, specs))]
+    for c in singles:
+        c.em_step(2)
+    stream.synchronize()
+
+    def run_all():
+        for c in singles:
+            c.em_step(iters)
+
+    t_seq = _time(run_all, stream, 2)
+    for c in singles:
+        c.close()
+    updates = sum(s["F"] * s["T"] * s["N"] for s in specs) * iters
+    bins = sum(s["F"] * s["T"] for s in specs)
+    out = {"metric": "EM TF-bin*source updates/s", "value": updates / (t_batch * 1e-3), "unit": "updates/s",
+           "n_gpus": 1, "steps": max(2, args.steps // 5), "warmup": 1, "ms_per_step": t_batch,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "batch: 256 mixtures, T~U{200..2000}, M in {2,3,4}, N in {M+1,M+2}, F=513, "
+                                  "%d IP+EM iterations, one persistent launch" % iters,
+                      "iters": iters, "tf_bins": bins, "threads": threads, "bins_per_thread": bpt,
+                      "sequential_ms": t_seq, "speedup_vs_sequential": t_seq / t_batch,
+                      "sequential_updates_per_s": updates / (t_seq * 1e-3)}}
+    print(json.dumps(out))
+
+
+def bench_large(args):
+    """M=8, N=10, F=1025, T=4000 (wide kernel family)."""
+    import torch
+
+    from paper_2101_08563_amd import FastFCA
+    from paper_2101_08563_amd.fastfca import synth_mixture
+
+    F, T, M, N, iters = 1025, 4000, 8, 10, args.iters
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        x = synth_mixture(F, T, M, N, rank=8, diffuse=0.05, seed=3, stream=stream)
+    stream.synchronize()
+    ctx = FastFCA(x, N, seed=3, stream=stream)
+    ctx.em_step(1)
+    ctx.sync()
+    t = _time(lambda: ctx.em_step(iters), stream, 3)
+    threads, bpt = ctx.get_config()
+    ll = ctx.loglik()
+    ctx.close()
+    updates = F * T * N * iters
+    flops = em_flops_per_bin(M, N) * F * T * iters
+    out = {"metric": "EM TF-bin*source updates/s", "value": updates / (t * 1e-3), "unit": "updates/s", "n_gpus": 1,
+           "steps": 3, "warmup": 1, "ms_per_step": t, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "large array: M=8 N=10 F=1025 T=4000, %d IP+EM iterations" % iters,
+                      "threads": threads, "bins_per_thread": bpt, "ll_per_bin": ll},
+           "roofline": {"kernel": "em_wide_kernel<8,10,%d>" % bpt, "bound": "alu",
+                        "achieved": flops / (t * 1e-3) / 1e12, "peak": FP32_FMA_PEAK / 1e12, "unit": "TFLOP/s",
+                        "frac": flops / (t * 1e-3) / FP32_FMA_PEAK, "traffic": None,
+                        "hbm_GBps_algorithmic": (16 * M * iters + 8 * N) * F * T / (t * 1e-3) / 1e9}}
     print(json.dumps(out))
 
 

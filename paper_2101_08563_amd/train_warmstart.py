@@ -16,7 +16,10 @@ Evaluation (per held-out mixture): LL* = the plain fit's log-likelihood per
 bin after --conv-iters iterations; iterations (and wall time) to reach
 LL* - 1e-2 from (a) the seeded initialization, (b) the network's warm start
 (P0, exp(lambda_hat), exp(v_hat)) and (c) a whitening-only start (P0,
-lambda = 1, v = whitened power / N). The warm start is judged by its initial
+lambda = 1, v = whitened power / N); for diagnosis also (d) the plain fit's
+own targets fed back through the warm-start path (a perfect network), (e)
+its lambda with the power-based v and (f) the network's lambda with the
+power-based v. The warm start is judged by its initial
 log-likelihood: if it is not finite or below that of the seeded start, the
 seeded start is used (fallback).
 """
@@ -83,7 +86,19 @@ def _time_em(ctx, k, reps=3):
     return best
 
 
+def _med(res, key):
+    a = np.array([r[key] if r[key] is not None else np.nan for r in res], float)
+    return float(np.nanmedian(a)) if np.isfinite(a).any() else None
+
+
 def cmd_eval(args):
+    summary = evaluate(args.weights, args.n_eval, args.conv_iters, args.batch, args.out)
+    return summary
+
+
+def evaluate(weights, n_eval, conv_iters, batch, out=""):
+    """Run the evaluation arms on n_eval held-out mixtures; returns the summary dict."""
+    args = argparse.Namespace(weights=weights, n_eval=n_eval, conv_iters=conv_iters, batch=batch, out=out)
     net = ConvNet.load(args.weights)
     res = []
     t0 = time.time()
@@ -115,7 +130,21 @@ def cmd_eval(args):
         p_init = [plain.get_params(b) for b in range(len(xs))]
         plain.em_step(args.conv_iters)
         tr_plain = [plain.ll_trace(b) for b in range(len(xs))]
+        # (d) a perfect network: the plain fit's own targets fed back through
+        # the warm-start path (an upper bound on what the network can gain)
+        probs_p, lam_perfect = [], []
+        for b, x in enumerate(xs):
+            P, lam, v = plain.get_params(b)
+            P0, _ = warmstart.features(x)
+            tv, tl = warmstart.targets(P, lam, v, P0)
+            lam_p, v_p = warmstart.apply_outputs(tv, tl.view(F, N, M), M)
+            probs_p.append(dict(x=x, N=N, P0=P0, lam0=lam_p, v0=v_p))
+            lam_perfect.append(lam_p)
         plain.close()
+        perfect = FastFCA.from_batch(probs_p)
+        perfect.em_step(args.conv_iters)
+        tr_perf = [perfect.ll_trace(b) for b in range(len(xs))]
+        perfect.close()
         # (b) warm start, (c) whitening only
         probs_w, probs_h, judged = [], [], []
         for b, x in enumerate(xs):
@@ -139,13 +168,25 @@ def cmd_eval(args):
         heur.em_step(args.conv_iters)
         tr_heur = [heur.ll_trace(b) for b in range(len(xs))]
         heur.close()
+        # (e) perfect lambda with the power-based v, (f) network lambda with the power-based v
+        pl = FastFCA.from_batch([dict(ph, lam0=lp) for ph, lp in zip(probs_h, lam_perfect)])
+        pl.em_step(args.conv_iters)
+        tr_pl = [pl.ll_trace(b) for b in range(len(xs))]
+        pl.close()
+        nl = FastFCA.from_batch([dict(ph, lam0=pw["lam0"]) for ph, pw in zip(probs_h, probs_w)])
+        nl.em_step(args.conv_iters)
+        tr_nl = [nl.ll_trace(b) for b in range(len(xs))]
+        nl.close()
         for b, i in enumerate(ids):
             llstar = float(tr_plain[b][-1])
             kp = _iters_to(tr_plain[b], llstar - TOL)
             kw = _iters_to(tr_warm[b], llstar - TOL)
             kh = _iters_to(tr_heur[b], llstar - TOL)
+            kpf = _iters_to(tr_perf[b], llstar - TOL)
             res.append(dict(id=i, ll_star=llstar, ll_warm_final=float(tr_warm[b][-1]), k_plain=kp, k_warm=kw,
-                            k_heur=kh, warm_used=bool(judged[b]), ll0_plain=ll_plain0[b], ll0_warm=ll_warm0[b]))
+                            k_heur=kh, k_perfect=kpf, k_perfect_lam=_iters_to(tr_pl[b], llstar - TOL),
+                            k_net_lam=_iters_to(tr_nl[b], llstar - TOL), warm_used=bool(judged[b]),
+                            ll0_plain=ll_plain0[b], ll0_warm=ll_warm0[b]))
         log("eval %d/%d mixtures (%.1f s)" % (len(res), args.n_eval, time.time() - t0))
 
     def wall(k, extra=0.0):
@@ -154,6 +195,7 @@ def cmd_eval(args):
     kp = np.array([r["k_plain"] for r in res], float)
     kw = np.array([r["k_warm"] if r["k_warm"] is not None else np.nan for r in res], float)
     kh = np.array([r["k_heur"] if r["k_heur"] is not None else np.nan for r in res], float)
+    kpf = np.array([r["k_perfect"] if r["k_perfect"] is not None else np.nan for r in res], float)
     wp = np.array([wall(r["k_plain"]) for r in res], float)
     ww = np.array([wall(r["k_warm"], t_ws) if r["k_warm"] is not None else np.nan for r in res], float)
     summary = {
@@ -161,6 +203,9 @@ def cmd_eval(args):
         "em_ms_per_iter": t_iter, "em_ms_per_call": t_fixed, "warmstart_ms": t_ws,
         "plain_iters_median": float(np.nanmedian(kp)), "warm_iters_median": float(np.nanmedian(kw)),
         "heur_iters_median": float(np.nanmedian(kh)) if np.isfinite(kh).any() else None,
+        "perfect_net_iters_median": float(np.nanmedian(kpf)) if np.isfinite(kpf).any() else None,
+        "perfect_lambda_power_v_iters_median": _med(res, "k_perfect_lam"),
+        "net_lambda_power_v_iters_median": _med(res, "k_net_lam"),
         "plain_ms_median": float(np.nanmedian(wp)), "warm_ms_median": float(np.nanmedian(ww)),
         "warm_reached_frac": float(np.isfinite(kw).mean()), "heur_reached_frac": float(np.isfinite(kh).mean()),
         "warm_faster_frac": float(np.nanmean(np.where(np.isfinite(ww), ww < wp, False))),
@@ -171,6 +216,7 @@ def cmd_eval(args):
     if args.out:
         with open(args.out, "w") as fh:
             json.dump({"summary": summary, "per_mixture": res}, fh)
+    return summary
 
 
 def main(argv=None):
