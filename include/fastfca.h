@@ -193,6 +193,20 @@ int fastfca_set_config(fastfca_ctx *c, int threads, int bins_per_thread);
  */
 int fastfca_autotune(fastfca_ctx *c, int n_iter, const char *cache_path);
 
+/* Update of L and H inside each iteration of fastfca_em_step. */
+enum {
+    FASTFCA_ALGO_EM = 0, /* Algorithm 1 (IP+EM): sources updated in order, the default */
+    FASTFCA_ALGO_MM = 1  /* Algorithm 2 (IP+MM): multiplicative square-root rules, L then H */
+};
+
+/*
+ * fastfca_set_algorithm -- choose the L/H update of later fastfca_em_step
+ * calls (Sec. IV-E: Algorithm 1 or Algorithm 2; the IP update of P and the
+ * log-likelihood are shared). IP+MM is compiled for the shapes that run on
+ * chip (M <= 4, N <= 8, T <= 2048): E_UNSUPPORTED otherwise.
+ */
+int fastfca_set_algorithm(fastfca_ctx *c, int algo);
+
 /* Launch configuration in effect for the (M,N) class of mixture b. */
 int fastfca_get_config(const fastfca_ctx *c, int b, int *threads, int *bins_per_thread);
 

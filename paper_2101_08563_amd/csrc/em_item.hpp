@@ -27,6 +27,7 @@
 
 #include "device.hpp"
 #include "internal.hpp"
+#include "ip_wave.hpp"
 
 namespace ffca {
 
@@ -43,134 +44,9 @@ struct EmSmem {
     double qtot[kRedW];
     double2 Pd[kMaxM * kMaxM];
     float2 P32[kMaxM * kMaxM];
-    double2 Qm[kMaxM * kMaxM];   // IP scratch: Q_m as a full matrix
-    double2 A[kMaxM * kMaxM];    // IP scratch: P^H Q_m, then its elimination
-    double2 w[kMaxM];            // IP scratch: right-hand side / new column
+    IpLds<kMaxM> ip;             // IP scratch (lane-parallel sweep, M = 3, 4)
     int flag;
 };
-
-// IP sweep (Sec. IV-E): for m = 1..M in order, w_m <- (P^H Q_m)^{-1} e_m
-// (eq:ip1, Gaussian elimination with partial pivoting) and
-// w_m <- w_m / sqrt(w_m^H Q_m w_m) (eq:ip2); then ln|det P|^2. Run by every
-// lane of one wavefront on LDS-resident double precision matrices (all lanes
-// compute the same values, so the register footprint stays small and no lane
-// depends on another). Q_m arrives in sm.qtot as Hermitian real parameters,
-// already divided by T. Also refreshes the single precision copy sm.P32.
-template <int M>
-__device__ __forceinline__ int ip_sweep_lds(EmSmem &sm, double &ldet) {
-    double2 *P = sm.Pd;
-    double2 *Q = sm.Qm;
-    double2 *A = sm.A;
-    double2 *w = sm.w;
-#pragma unroll 1
-    for (int m = 0; m < M; ++m) {
-        const double *qm = sm.qtot + m * M * M;
-        bool finite = true;
-        for (int r = 0; r < M; ++r) {
-            Q[r * M + r] = make_double2(qm[r], 0.0);
-            finite = finite && fabs(qm[r]) < INFINITY;
-        }
-        {
-            int p = M;
-            for (int r = 0; r < M; ++r)
-                for (int c = r + 1; c < M; ++c) {
-                    Q[r * M + c] = make_double2(qm[p], qm[p + 1]);
-                    Q[c * M + r] = make_double2(qm[p], -qm[p + 1]);
-                    finite = finite && fabs(qm[p]) < INFINITY && fabs(qm[p + 1]) < INFINITY;
-                    p += 2;
-                }
-        }
-        if (!finite) return ST_NONFINITE;
-        // A = P^H Q_m
-        double amax2 = 0.0;
-        for (int r = 0; r < M; ++r)
-            for (int c = 0; c < M; ++c) {
-                cd s = cmk(0.0, 0.0);
-                for (int k = 0; k < M; ++k) s = s + conjd(ld(P[k * M + r])) * ld(Q[k * M + c]);
-                A[r * M + c] = st(s);
-                amax2 = fmax(amax2, abs2(s));
-            }
-        for (int r = 0; r < M; ++r) w[r] = make_double2(r == m ? 1.0 : 0.0, 0.0);
-        if (!(amax2 > 0.0) || !(amax2 < INFINITY)) return ST_SINGULAR;
-        // forward elimination with partial pivoting
-#pragma unroll 1
-        for (int k = 0; k < M; ++k) {
-            int piv = k;
-            double best = abs2(ld(A[k * M + k]));
-            for (int i = k + 1; i < M; ++i) {
-                const double a = abs2(ld(A[i * M + k]));
-                if (a > best) {
-                    best = a;
-                    piv = i;
-                }
-            }
-            if (!(best >= kPivotTol * kPivotTol * amax2)) return ST_SINGULAR;
-            if (piv != k) {
-                for (int j = 0; j < M; ++j) {
-                    const double2 t = A[k * M + j];
-                    A[k * M + j] = A[piv * M + j];
-                    A[piv * M + j] = t;
-                }
-                const double2 t = w[k];
-                w[k] = w[piv];
-                w[piv] = t;
-            }
-            const cd akk = ld(A[k * M + k]);
-            for (int i = k + 1; i < M; ++i) {
-                const cd l = cdiv(ld(A[i * M + k]), akk);
-                for (int j = k; j < M; ++j) A[i * M + j] = st(ld(A[i * M + j]) - l * ld(A[k * M + j]));
-                w[i] = st(ld(w[i]) - l * ld(w[k]));
-            }
-        }
-        for (int i = M - 1; i >= 0; --i) {
-            cd s = ld(w[i]);
-            for (int j = i + 1; j < M; ++j) s = s - ld(A[i * M + j]) * ld(w[j]);
-            w[i] = st(cdiv(s, ld(A[i * M + i])));
-        }
-        // normalization w^H Q_m w = 1
-        double qq = 0.0;
-        for (int r = 0; r < M; ++r) {
-            cd s = cmk(0.0, 0.0);
-            for (int c = 0; c < M; ++c) s = s + ld(Q[r * M + c]) * ld(w[c]);
-            qq += (conjd(ld(w[r])) * s).re;
-        }
-        if (!(qq > 0.0) || !(qq < INFINITY)) return ST_SINGULAR;
-        const double inv = 1.0 / sqrt(qq);
-        for (int r = 0; r < M; ++r) P[r * M + m] = st(inv * ld(w[r]));
-    }
-    // ln|det P|^2 by elimination of a copy
-    for (int i = 0; i < M * M; ++i) A[i] = P[i];
-    double acc = 0.0;
-#pragma unroll 1
-    for (int k = 0; k < M; ++k) {
-        int piv = k;
-        double best = abs2(ld(A[k * M + k]));
-        for (int i = k + 1; i < M; ++i) {
-            const double a = abs2(ld(A[i * M + k]));
-            if (a > best) {
-                best = a;
-                piv = i;
-            }
-        }
-        if (!(best > 0.0)) return ST_SINGULAR;
-        if (piv != k)
-            for (int j = 0; j < M; ++j) {
-                const double2 t = A[k * M + j];
-                A[k * M + j] = A[piv * M + j];
-                A[piv * M + j] = t;
-            }
-        const cd akk = ld(A[k * M + k]);
-        for (int i = k + 1; i < M; ++i) {
-            const cd l = cdiv(ld(A[i * M + k]), akk);
-            for (int j = k; j < M; ++j) A[i * M + j] = st(ld(A[i * M + j]) - l * ld(A[k * M + j]));
-        }
-        acc += log(best);
-    }
-    ldet = acc;
-    for (int i = 0; i < M * M; ++i)
-        sm.P32[i] = make_float2(static_cast<float>(P[i].x), static_cast<float>(P[i].y));
-    return ST_OK;
-}
 
 // Fixed-order sum of the 16 wave slots of one reduced value.
 __device__ __forceinline__ float sum_slots(const float *p) {
@@ -187,11 +63,6 @@ __device__ __forceinline__ double sum_slots(const double *p) {
     for (int i = 0; i < 8; ++i) s[i] = p[2 * i] + p[2 * i + 1];
     return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
-
-// Real parameters of a Hermitian M x M matrix: M diagonal entries, then
-// (re, im) of each upper-triangle entry (r < c) in row-major order.
-template <int M>
-__device__ __forceinline__ constexpr int herm_n() { return M * M; }
 
 // IP sweep for M = 2 in registers (every lane of wave 0 computes the same
 // values): the 2 x 2 system of eq:ip1 is solved by its adjugate (Cramer's
@@ -254,7 +125,7 @@ __device__ __forceinline__ int ip_sweep_reg2(EmSmem &sm, const double (&q)[8], d
 }
 
 template <int M, int N, int BPT>
-__device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, EmSmem &sm) {
+__device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo, EmSmem &sm) {
     constexpr int NQ = M * M * M;
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
@@ -380,8 +251,8 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, EmSmem &
                     if (lane < NQ) sm.qtot[lane] = static_cast<double>(sum_slots(sm.red[buf][lane])) * invT;
                     __threadfence_block();
                     __builtin_amdgcn_wave_barrier();
-                    // IP sweep in double precision (LDS-resident matrices)
-                    status = ip_sweep_lds<M>(sm, ldet);
+                    // lane-parallel IP sweep in double precision
+                    status = ip_wave<M, kMaxM>(sm.qtot, sm.Pd, sm.P32, sm.ip, ldet);
                 }
                 if (status == ST_OK) ldet_prev = ldet;
             }
@@ -416,7 +287,78 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, EmSmem &
             }
         }
 
-        // ---------------- phase C: EM over sources, in order
+        // ---------------- phase C (Algorithm 2): MM update of L, then of H
+        if (algo == kAlgoMM) {
+            // numerators / denominators of the L rule: sum_t U v / sigma^4, sum_t v / sigma^2
+            float nd[2 * N * M];
+#pragma unroll
+            for (int i = 0; i < 2 * N * M; ++i) nd[i] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < BPT; ++k) {
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    float s = 0.0f;
+#pragma unroll
+                    for (int nn = 0; nn < N; ++nn) s = fmaf(vr[k][nn], lam[nn][m], s);
+                    const float is = valid[k] ? rcp(s) : 0.0f;
+                    const float ua = U[k][m] * is * is;
+#pragma unroll
+                    for (int n = 0; n < N; ++n) {
+                        nd[n * M + m] = fmaf(ua, vr[k][n], nd[n * M + m]);
+                        nd[N * M + n * M + m] = fmaf(is, vr[k][n], nd[N * M + n * M + m]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 2 * N * M; ++i) nd[i] = wave_sum(nd[i]);
+            if (lane == 0) {
+#pragma unroll
+                for (int i = 0; i < 2 * N * M; ++i) sm.red[buf][i][wid] = nd[i];
+            }
+            __syncthreads();
+            const float mine = lane < 2 * N * M ? sum_slots(sm.red[buf][lane]) : 0.0f;
+            bool good = true;
+#pragma unroll
+            for (int n = 0; n < N; ++n)
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    const float num = readlane_f(mine, n * M + m);
+                    const float den = readlane_f(mine, N * M + n * M + m);
+                    const float l = lam[n][m] * sqrtf(num / den);
+                    good = good && (l > 0.0f) && (l < INFINITY);
+                    lam[n][m] = l;
+                }
+            buf ^= 1;
+            if (!good) {
+                status = ST_NONFINITE;
+                break;
+            }
+            // H rule with the new L (local to each bin)
+#pragma unroll
+            for (int k = 0; k < BPT; ++k) {
+                float num[N], den[N];
+#pragma unroll
+                for (int n = 0; n < N; ++n) num[n] = den[n] = 0.0f;
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    float s = 0.0f;
+#pragma unroll
+                    for (int nn = 0; nn < N; ++nn) s = fmaf(vr[k][nn], lam[nn][m], s);
+                    const float is = rcp(s);
+                    const float ua = U[k][m] * is * is;
+#pragma unroll
+                    for (int n = 0; n < N; ++n) {
+                        num[n] = fmaf(lam[n][m], ua, num[n]);
+                        den[n] = fmaf(lam[n][m], is, den[n]);
+                    }
+                }
+#pragma unroll
+                for (int n = 0; n < N; ++n) vr[k][n] = valid[k] ? vr[k][n] * sqrtf(num[n] / den[n]) : 1.0f;
+            }
+            continue;
+        }
+
+        // ---------------- phase C (Algorithm 1): EM over sources, in order
 #pragma unroll
         for (int n = 0; n < N; ++n) {
             if (status != ST_OK) continue;

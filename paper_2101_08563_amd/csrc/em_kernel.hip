@@ -11,7 +11,7 @@ __global__ void __launch_bounds__(kResidentBins / BPT) em_kernel(EmLaunch a) {
     __shared__ EmSmem sm;
     const WorkItem &it = a.items[blockIdx.x];
     if (*it.status != ST_OK) return;  // frozen after an earlier failure
-    em_item<M, N, BPT>(it, a.n_iter, sm);
+    em_item<M, N, BPT>(it, a.n_iter, a.algo, sm);
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(kResidentBins / BPT) em_persistent_kernel(EmLa
         if (*it.status != ST_OK) continue;
         switch (it.M * 16 + it.N) {
 #define FFCA_CASE(MM, NN) \
-    case MM * 16 + NN: em_item<MM, NN, BPT>(it, a.n_iter, sm); break;
+    case MM * 16 + NN: em_item<MM, NN, BPT>(it, a.n_iter, a.algo, sm); break;
             FFCA_PERSISTENT_CLASSES(FFCA_CASE)
 #undef FFCA_CASE
             default: break;

@@ -24,6 +24,7 @@
 
 #include "device.hpp"
 #include "internal.hpp"
+#include "ip_wave.hpp"
 
 namespace ffca {
 
@@ -47,150 +48,9 @@ struct WideSmem {
     double qtot[kWideMaxM * kWideMaxM * kWideMaxM];
     double2 Pd[kWideMaxM * kWideMaxM];
     float2 P32[kWideMaxM * kWideMaxM];
-    double2 Qd[kWideMaxM * kWideMaxM * kWideMaxM];
-    double2 A[kWideMaxM * (kWideMaxM + 1)];
-    double2 colk[kWideMaxM];
+    IpLds<kWideMaxM> ip;
     int flag;
 };
-
-__device__ __forceinline__ double wave_max(double v) {
-    v = fmax(v, dpp_d<0xB1>(v));
-    v = fmax(v, dpp_d<0x4E>(v));
-    v = fmax(v, dpp_d<0x141>(v));
-    v = fmax(v, dpp_d<0x140>(v));
-    return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
-}
-
-// Index (r, c), r < c, of the p-th strictly upper entry in row-major order.
-template <int M>
-__device__ __forceinline__ void upper_pair(int p, int &r, int &c) {
-    r = 0;
-    int rowlen = M - 1;
-    while (p >= rowlen) {
-        p -= rowlen;
-        ++r;
-        --rowlen;
-    }
-    c = r + 1 + p;
-}
-template <int M>
-__device__ __forceinline__ int upper_index(int r, int c) {  // r < c
-    return r * (2 * M - r - 1) / 2 + (c - r - 1);
-}
-
-// Lane-parallel IP sweep on wave 0 (all 64 lanes call it). Q_m arrive in
-// sm.qtot as Hermitian real parameters divided by T; P is updated in sm.Pd
-// and sm.P32. Gauss-Jordan on [A | e_m] in LDS: every step is a few LDS
-// phases of one wavefront, which executes its LDS instructions in order.
-template <int M>
-__device__ __noinline__ int ip_wave(WideSmem &sm, double &ldet) {
-    constexpr int M2 = M * M;
-    constexpr int W = M + 1;  // row stride of the augmented matrix
-    const int lane = threadIdx.x & 63;
-    const bool el = lane < M2;
-    const int r = lane / M, c = lane % M;
-    bool finite = true;
-    for (int i = lane; i < M * M2; i += 64) {
-        const int m = i / M2, rr = (i / M) % M, cc = i % M;
-        const double *q = sm.qtot + m * M2;
-        double2 v;
-        if (rr == cc) {
-            v = make_double2(q[rr], 0.0);
-        } else {
-            const int lo = rr < cc ? rr : cc, hi = rr < cc ? cc : rr;
-            const int p = upper_index<M>(lo, hi);
-            const double re = q[M + 2 * p], im = q[M + 2 * p + 1];
-            v = make_double2(re, rr < cc ? im : -im);
-        }
-        finite = finite && fabs(v.x) < INFINITY && fabs(v.y) < INFINITY;
-        sm.Qd[i] = v;
-    }
-    if (__any(!finite)) return ST_NONFINITE;
-#pragma unroll 1
-    for (int m = 0; m < M; ++m) {
-        double a2 = 0.0;
-        if (el) {
-            cd s = cmk(0.0, 0.0);
-            for (int k = 0; k < M; ++k) s = s + conjd(ld(sm.Pd[k * M + r])) * ld(sm.Qd[m * M2 + k * M + c]);
-            sm.A[r * W + c] = st(s);
-            a2 = abs2(s);
-        }
-        if (lane < M) sm.A[lane * W + M] = make_double2(lane == m ? 1.0 : 0.0, 0.0);
-        const double amax2 = wave_max(a2);
-        if (!(amax2 > 0.0) || !(amax2 < INFINITY)) return ST_SINGULAR;
-#pragma unroll 1
-        for (int k = 0; k < M; ++k) {
-            int p = k;
-            double best = abs2(ld(sm.A[k * W + k]));
-            for (int i = k + 1; i < M; ++i) {
-                const double a = abs2(ld(sm.A[i * W + k]));
-                if (a > best) {
-                    best = a;
-                    p = i;
-                }
-            }
-            if (!(best >= kPivotTol * kPivotTol * amax2)) return ST_SINGULAR;
-            if (p != k && lane <= M) {
-                const double2 t = sm.A[k * W + lane];
-                sm.A[k * W + lane] = sm.A[p * W + lane];
-                sm.A[p * W + lane] = t;
-            }
-            const cd piv = ld(sm.A[k * W + k]);
-            const cd ipiv = rcp_d(abs2(piv)) * conjd(piv);
-            if (lane <= M) sm.A[k * W + lane] = st(ld(sm.A[k * W + lane]) * ipiv);
-            if (lane < M) sm.colk[lane] = sm.A[lane * W + k];
-            for (int i2 = lane; i2 < M * W; i2 += 64) {
-                const int i = i2 / W, j = i2 % W;
-                if (i != k) sm.A[i * W + j] = st(ld(sm.A[i * W + j]) - ld(sm.colk[i]) * ld(sm.A[k * W + j]));
-            }
-        }
-        // w = last column; normalize so that w^H Q_m w = 1
-        double qt = 0.0;
-        if (el) {
-            const cd wr = ld(sm.A[r * W + M]), wc = ld(sm.A[c * W + M]);
-            qt = (conjd(wr) * ld(sm.Qd[m * M2 + r * M + c]) * wc).re;
-        }
-        const double qq = wave_sum(qt);
-        if (!(qq > 0.0) || !(qq < INFINITY)) return ST_SINGULAR;
-        const double inv = rsqrt_d(qq);
-        if (lane < M) sm.Pd[lane * M + m] = st(inv * ld(sm.A[lane * W + M]));
-    }
-    // ln|det P|^2: elimination with partial pivoting on a copy of P
-    if (el) sm.A[r * W + c] = sm.Pd[lane];
-    double acc = 0.0;
-#pragma unroll 1
-    for (int k = 0; k < M; ++k) {
-        int p = k;
-        double best = abs2(ld(sm.A[k * W + k]));
-        for (int i = k + 1; i < M; ++i) {
-            const double a = abs2(ld(sm.A[i * W + k]));
-            if (a > best) {
-                best = a;
-                p = i;
-            }
-        }
-        if (!(best > 0.0)) return ST_SINGULAR;
-        acc += log(best);
-        if (p != k && lane < M) {
-            const double2 t = sm.A[k * W + lane];
-            sm.A[k * W + lane] = sm.A[p * W + lane];
-            sm.A[p * W + lane] = t;
-        }
-        const cd piv = ld(sm.A[k * W + k]);
-        const cd ipiv = rcp_d(abs2(piv)) * conjd(piv);
-        if (lane < M) sm.colk[lane] = st(ld(sm.A[lane * W + k]) * ipiv);
-        for (int i2 = lane; i2 < M * M; i2 += 64) {
-            const int i = i2 / M, j = i2 % M;
-            if (i > k) sm.A[i * W + j] = st(ld(sm.A[i * W + j]) - ld(sm.colk[i]) * ld(sm.A[k * W + j]));
-        }
-    }
-    ldet = acc;
-    if (el) {
-        const double2 p = sm.Pd[lane];
-        sm.P32[lane] = make_float2(static_cast<float>(p.x), static_cast<float>(p.y));
-    }
-    return ST_OK;
-}
 
 template <int M, int N, int BPT>
 __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, WideSmem &sm) {
@@ -325,7 +185,7 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, Wid
             }
             if (!last && status == ST_OK) {
                 double ldet = 0.0;
-                status = ip_wave<M>(sm, ldet);
+                status = ip_wave<M, kWideMaxM>(sm.qtot, sm.Pd, sm.P32, sm.ip, ldet);
                 if (status == ST_OK) ldet_prev = ldet;
             }
             if (lane == 0) sm.flag = status;

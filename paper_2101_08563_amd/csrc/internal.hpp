@@ -31,11 +31,16 @@ constexpr int kResidentBins = 2048;
 // Relative pivot threshold of the double precision IP solve.
 constexpr double kPivotTol = 1e-12;
 
+// Update of L and H inside an iteration: Algorithm 1 (EM, sequential over
+// sources) or Algorithm 2 (MM, all sources at once).
+enum : int { kAlgoEM = 0, kAlgoMM = 1 };
+
 struct EmLaunch {
     const WorkItem *items;  // items handled by this launch
     int n_items;
     int n_iter;
     int *queue;             // persistent launch: next-item counter (nullptr otherwise)
+    int algo;               // kAlgoEM or kAlgoMM
 };
 
 // Launch one EM kernel (Algorithm 1 for n_iter iterations) over `n_items`

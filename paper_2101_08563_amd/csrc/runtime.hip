@@ -74,6 +74,7 @@ struct fastfca_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int graph_n_iter = -1;
+    int algo = kAlgoEM;
     std::string err;
     char arch[64] = {0};
 };
@@ -416,14 +417,14 @@ int create(fastfca_ctx **out, int B, const fastfca_problem *probs, uint64_t seed
 int record_em(fastfca_ctx *c, int n_iter) {
     if (c->persistent) {
         HIPCHK(c, launch_fill_int(c->d_queue, 1, 0, c->stream));
-        EmLaunch a{c->d_items, static_cast<int>(c->h_items.size()), n_iter, c->d_queue};
+        EmLaunch a{c->d_items, static_cast<int>(c->h_items.size()), n_iter, c->d_queue, c->algo};
         HIPCHK(c, launch_em_persistent(a, c->p_threads, c->p_bpt, c->p_grid, c->stream));
         return FASTFCA_OK;
     }
     for (size_t k = 0; k < c->classes.size(); ++k) {
         const auto &cc = c->classes[k];
         EmLaunch a{c->d_items + c->class_first[k], static_cast<int>(cc.items.size()), n_iter,
-                   nullptr};
+                   nullptr, c->algo};
         if (cc.wide)
             HIPCHK(c, launch_em_wide(cc.M, cc.N, cc.bpt, cc.threads, a,
                                      static_cast<int>(cc.items.size()), c->stream));
@@ -637,6 +638,21 @@ int fastfca_set_config(fastfca_ctx *c, int threads, int bins_per_thread) {
             cc.bpt = bins_per_thread;
         }
     }
+    drop_graph(c);
+    return FASTFCA_OK;
+}
+
+int fastfca_set_algorithm(fastfca_ctx *c, int algo) {
+    if (!c) return FASTFCA_E_ARG;
+    if (algo != FASTFCA_ALGO_EM && algo != FASTFCA_ALGO_MM)
+        return set_err(c, FASTFCA_E_ARG, "unknown algorithm %d", algo);
+    if (algo == FASTFCA_ALGO_MM)
+        for (const auto &cc : c->classes)
+            if (cc.wide)
+                return set_err(c, FASTFCA_E_UNSUPPORTED,
+                               "IP+MM is compiled for the resident family only (M<=4, N<=8, T<=2048); "
+                               "M=%d N=%d T=%d", cc.M, cc.N, cc.Tmax);
+    c->algo = algo == FASTFCA_ALGO_MM ? kAlgoMM : kAlgoEM;
     drop_graph(c);
     return FASTFCA_OK;
 }

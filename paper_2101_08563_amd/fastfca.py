@@ -38,6 +38,7 @@ SIGNATURES = {
     "fastfca_set_config": (_i, [_vp, _i, _i]),
     "fastfca_autotune": (_i, [_vp, _i, ctypes.c_char_p]),
     "fastfca_get_config": (_i, [_vp, _i, _pi, _pi]),
+    "fastfca_set_algorithm": (_i, [_vp, _i]),
     "fastfca_synth_mixture": (_i, [_vp, _i, _i, _i, _i, _i, ctypes.c_float, _u64, _vp]),
     "fastfca_last_error": (ctypes.c_char_p, [_vp]),
     "fastfca_destroy": (None, [_vp]),
@@ -227,6 +228,11 @@ class FastFCA:
 
     def set_config(self, threads=0, bins_per_thread=0):
         self._chk(self._lib.fastfca_set_config(self._ctx, int(threads), int(bins_per_thread)))
+
+    def set_algorithm(self, algo):
+        """'em' (Algorithm 1, default) or 'mm' (Algorithm 2)."""
+        code = {"em": 0, "mm": 1}[algo] if isinstance(algo, str) else int(algo)
+        self._chk(self._lib.fastfca_set_algorithm(self._ctx, code))
 
     def get_config(self, b=0):
         th, bpt = ctypes.c_int(), ctypes.c_int()

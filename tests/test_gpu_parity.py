@@ -227,3 +227,34 @@ def test_zero_frequency_is_reported_singular():
     keep = [0, 1, 2, 4]
     Po, lo, vo, _ = oracle.fit(x[keep], P0[keep], lam0[keep], v0[keep], 5)
     assert rel(v[keep], vo) < 1e-4
+
+
+@pytest.mark.parametrize("M,N,T,F", [(2, 3, 1000, 64), (3, 4, 700, 9), (4, 6, 400, 7), (2, 2, 77, 5)])
+def test_ip_mm_algorithm2_parity(M, N, T, F):
+    """Algorithm 2 (IP+MM) against the oracle's IP+MM."""
+    x, P0, lam0, v0 = make_case(F, T, M, N, config_id=90 + M, mixture_id=N)
+    xd, Pd, ld, vd = to_dev(x, P0, lam0, v0)
+    ctx = FastFCA(xd, N, Pd, ld, vd)
+    ctx.set_algorithm("mm")
+    ctx.em_step(30)
+    ctx.sync()
+    trace = ctx.ll_trace()
+    ll = ctx.loglik()
+    P, lam, v = (t.cpu().numpy() for t in ctx.get_params())
+    ctx.close()
+    Po, lo, vo, tro = oracle.fit(x, P0, lam0, v0, 30, algo=1, trace=True)
+    llo, _ = oracle.loglik(x, Po, lo, vo)
+    errs = dict(v=rel(v, vo), lam=rel(lam, lo), P=rel(P, Po), ll=abs(ll - llo))
+    print("mm", M, N, T, errs, flush=True)
+    assert errs["v"] < REL_TOL and errs["lam"] < REL_TOL and errs["P"] < REL_TOL and errs["ll"] < LL_TOL, errs
+    assert np.abs(trace - tro).max() < 1e-4
+    assert np.diff(trace).min() > -1e-5
+
+
+def test_ip_mm_rejected_for_wide_shapes():
+    x, P0, lam0, v0 = make_case(3, 300, 6, 7, config_id=99)
+    ctx = FastFCA(*to_dev(x), 7)
+    with pytest.raises(FastFCAError) as e:
+        ctx.set_algorithm("mm")
+    assert e.value.code == -7
+    ctx.close()
