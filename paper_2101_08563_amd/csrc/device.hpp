@@ -41,21 +41,61 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
                                 (static_cast<unsigned int>(lo)));
 }
 
-// Sum over the 64 lanes of a wavefront; the result is wave-uniform.
-// Every lane must be active.
-__device__ __forceinline__ float wave_sum(float v) {
+// Sum over each 16-lane row: afterwards every lane of a row holds the row's
+// sum, bitwise identical across the row. Every lane must be active.
+__device__ __forceinline__ float row_sum(float v) {
     v += dpp_f<0xB1>(v);
     v += dpp_f<0x4E>(v);
     v += dpp_f<0x141>(v);
     v += dpp_f<0x140>(v);
-    return (readlane_f(v, 0) + readlane_f(v, 16)) + (readlane_f(v, 32) + readlane_f(v, 48));
+    return v;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
+__device__ __forceinline__ double row_sum(double v) {
     v += dpp_d<0xB1>(v);
     v += dpp_d<0x4E>(v);
     v += dpp_d<0x141>(v);
     v += dpp_d<0x140>(v);
+    return v;
+}
+
+// Sum over the 64 lanes of a wavefront, complete in lane 63 only: after the
+// row sums, row_bcast:15 folds row 0 into row 1 and row 2 into row 3, then
+// row_bcast:31 folds row 1 into rows 2 and 3 (rows outside the row mask add
+// zero). Order: (r3 + r2) + (r1 + r0).
+__device__ __forceinline__ float wave_sum_last(float v) {
+    v = row_sum(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false));
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_last(double v) {
+    v = row_sum(v);
+    {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xffffffffLL), 0x142, 0xA, 0xF, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x142, 0xA, 0xF, false);
+        v += __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+    }
+    {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xffffffffLL), 0x143, 0xC, 0xF, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x143, 0xC, 0xF, false);
+        v += __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+    }
+    return v;
+}
+
+// Sum over the 64 lanes of a wavefront; the result is wave-uniform.
+// Every lane must be active.
+__device__ __forceinline__ float wave_sum(float v) {
+    v = row_sum(v);
+    return (readlane_f(v, 0) + readlane_f(v, 16)) + (readlane_f(v, 32) + readlane_f(v, 48));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    v = row_sum(v);
     return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
@@ -64,9 +104,9 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 
 // Natural log in single precision from the hardware log2 (v_log_f32) for
 // normal positive inputs; used only for the per-iteration likelihood trace.
-__device__ __forceinline__ float ln_fast(float x) {
-    return __builtin_amdgcn_logf(x) * 0.69314718055994531f;
-}
+constexpr float kLn2f = 0.69314718055994531f;
+__device__ __forceinline__ float log2_fast(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float ln_fast(float x) { return log2_fast(x) * kLn2f; }
 
 // Double precision 1/x and 1/sqrt(x) from the hardware estimates refined by
 // Newton steps (each step squares the relative error; two steps reach full

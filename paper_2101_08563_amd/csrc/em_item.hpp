@@ -36,32 +36,73 @@ constexpr int kMaxM = 4;            // resident family: M <= 4
 constexpr int kRedW = kMaxM * kMaxM * kMaxM;  // widest reduction (all Q_m, M = 4)
 constexpr double kLnPi = 1.1447298858494002;  // ln(pi)
 
+// Reduction slots per workgroup of a launch with BPT bins per thread: one
+// per wave of the largest workgroup it allows, at least 4.
+constexpr int wave_slots(int bpt) { return kResidentBins / bpt / 64 < 4 ? 4 : kResidentBins / bpt / 64; }
+
+// LDS of one workgroup. Phase A (the M^3 parameters of the Q_m and the
+// likelihood terms) leaves one partial per 16-lane row, four per wave, in
+// redq / red_d; each L reduction of phase C (M values, or the 2NM sums of the
+// multiplicative rule) one partial per wave in redc, double buffered so that
+// one barrier per reduction suffices. Slots of waves that do not exist stay
+// zero. RQ >= M^3, RC >= 2NM values; NWS wave slots.
+template <int RQ, int RC, int NWS>
 struct EmSmem {
-    // reduction partials, value-major with one slot per wave; slots of waves
-    // that do not exist stay zero so every sum runs over all 16 slots
-    alignas(16) float red[2][kRedW][kMaxWaves];
-    alignas(16) double red_d[2][kMaxWaves];
-    double qtot[kRedW];
+    static constexpr int kRowSlots = 4 * NWS;
+    static constexpr int kWaveSlots = NWS;
+    alignas(16) float redq[RQ][4 * NWS];
+    alignas(16) double red_d[4 * NWS];
+    alignas(16) float redc[2][RC][NWS];
+    double qtot[RQ];
     double2 Pd[kMaxM * kMaxM];
     float2 P32[kMaxM * kMaxM];
     IpLds<kMaxM> ip;             // IP scratch (lane-parallel sweep, M = 3, 4)
     int flag;
 };
 
-// Fixed-order sum of the 16 wave slots of one reduced value.
+// Fixed-order sum of the NS partials of one value, loaded in chunks of up to
+// 32 slots whose loads are all issued before the first add.
+template <int NS>
 __device__ __forceinline__ float sum_slots(const float *p) {
-    const float4 a = *reinterpret_cast<const float4 *>(p);
-    const float4 b = *reinterpret_cast<const float4 *>(p + 4);
-    const float4 c = *reinterpret_cast<const float4 *>(p + 8);
-    const float4 d = *reinterpret_cast<const float4 *>(p + 12);
-    return (((a.x + a.y) + (a.z + a.w)) + ((b.x + b.y) + (b.z + b.w))) +
-           (((c.x + c.y) + (c.z + c.w)) + ((d.x + d.y) + (d.z + d.w)));
-}
-__device__ __forceinline__ double sum_slots(const double *p) {
-    double s[8];
+    static_assert(NS % 4 == 0, "slots come in fours");
+    constexpr int C = NS < 32 ? NS / 4 : 8;
+    float tot = 0.0f;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) s[i] = p[2 * i] + p[2 * i + 1];
-    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    for (int c0 = 0; c0 < NS / 4; c0 += C) {
+        float s[C];
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const float4 a = *reinterpret_cast<const float4 *>(p + 4 * (c0 + i));
+            s[i] = (a.x + a.y) + (a.z + a.w);
+        }
+#pragma unroll
+        for (int h = 1; h < C; h *= 2)
+#pragma unroll
+            for (int i = 0; i + h < C; i += 2 * h) s[i] += s[i + h];
+        tot = c0 == 0 ? s[0] : tot + s[0];
+    }
+    return tot;
+}
+template <int NS>
+__device__ __forceinline__ double sum_slots(const double *p) {
+    constexpr int C = NS < 32 ? NS / 4 : 8;
+    double tot = 0.0;
+#pragma unroll
+    for (int c0 = 0; c0 < NS / 4; c0 += C) {
+        double s[C];
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const double2 a = *reinterpret_cast<const double2 *>(p + 4 * (c0 + i));
+            const double2 b = *reinterpret_cast<const double2 *>(p + 4 * (c0 + i) + 2);
+            s[i] = (a.x + a.y) + (b.x + b.y);
+        }
+#pragma unroll
+        for (int h = 1; h < C; h *= 2)
+#pragma unroll
+            for (int i = 0; i + h < C; i += 2 * h) s[i] += s[i + h];
+        tot = c0 == 0 ? s[0] : tot + s[0];
+    }
+    return tot;
 }
 
 // IP sweep for M = 2 in registers (every lane of wave 0 computes the same
@@ -69,7 +110,8 @@ __device__ __forceinline__ double sum_slots(const double *p) {
 // rule), which for a 2 x 2 matrix is the elimination result without row
 // exchanges; the pivot test compares |det| with the largest entry squared.
 // qsum: the 8 reduced Hermitian parameters (Q_1 then Q_2), already / T.
-__device__ __forceinline__ int ip_sweep_reg2(EmSmem &sm, const double (&q)[8], double &ldet) {
+template <class Smem>
+__device__ __forceinline__ int ip_sweep_reg2(Smem &sm, const double (&q)[8], double &ldet) {
     cd P[2][2];
     P[0][0] = ld(sm.Pd[0]);
     P[0][1] = ld(sm.Pd[1]);
@@ -124,30 +166,36 @@ __device__ __forceinline__ int ip_sweep_reg2(EmSmem &sm, const double (&q)[8], d
     return ST_OK;
 }
 
-template <int M, int N, int BPT>
-__device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo, EmSmem &sm) {
+template <int M, int N, int BPT, class Smem>
+__device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo, Smem &sm) {
     constexpr int NQ = M * M * M;
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
+    constexpr int NR = Smem::kRowSlots;
+    constexpr int NW = Smem::kWaveSlots;
     const int lane = tid & 63;
     const int wid = tid >> 6;
+    const bool row_lead = (lane & 15) == 0;
+    const int row_slot = 4 * wid + (lane >> 4);
     const int T = it.T;
     const float invTf = 1.0f / static_cast<float>(T);
     const double invT = 1.0 / static_cast<double>(T);
 
-    // ---- load the frequency's state
+    // ---- load the frequency's state. Bins t >= T hold x = 0 and h = 1: they
+    // add nothing to Q or U, and mk = 0 drops them from the other sums.
     float2 xr[BPT][M];
     float vr[BPT][N];
     float U[BPT][M];
-    bool valid[BPT];
+    float mk[BPT];
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {
         const int t = tid + k * nthr;
-        valid[k] = t < T;
+        const bool valid = t < T;
+        mk[k] = valid ? 1.0f : 0.0f;
 #pragma unroll
-        for (int r = 0; r < M; ++r) xr[k][r] = valid[k] ? it.x[t * M + r] : make_float2(0.f, 0.f);
+        for (int r = 0; r < M; ++r) xr[k][r] = valid ? it.x[t * M + r] : make_float2(0.f, 0.f);
 #pragma unroll
-        for (int n = 0; n < N; ++n) vr[k][n] = valid[k] ? it.v[t * N + n] : 1.0f;
+        for (int n = 0; n < N; ++n) vr[k][n] = valid ? it.v[t * N + n] : 1.0f;
 #pragma unroll
         for (int m = 0; m < M; ++m) U[k][m] = 0.0f;
     }
@@ -160,8 +208,9 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
         sm.Pd[tid] = it.P[tid];
     }
     if (tid == 0) sm.flag = ST_OK;
-    for (int i = tid; i < 2 * kRedW * kMaxWaves; i += nthr) (&sm.red[0][0][0])[i] = 0.0f;
-    if (tid < 2 * kMaxWaves) (&sm.red_d[0][0])[tid] = 0.0;
+    for (int i = tid; i < static_cast<int>(sizeof(sm.redq) / sizeof(float)); i += nthr) (&sm.redq[0][0])[i] = 0.0f;
+    for (int i = tid; i < static_cast<int>(sizeof(sm.redc) / sizeof(float)); i += nthr) (&sm.redc[0][0][0])[i] = 0.0f;
+    for (int i = tid; i < NR; i += nthr) sm.red_d[i] = 0.0;
     __syncthreads();
 
     double ldet_prev = 0.0;  // ln|det P|^2 of the iterate being evaluated (wave 0)
@@ -174,7 +223,8 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
         float q[NQ];
 #pragma unroll
         for (int i = 0; i < NQ; ++i) q[i] = 0.0f;
-        double llp = 0.0;
+        float lg2 = 0.0f;  // sum of log2 sigma^2 over this lane's bins
+        float uw = 0.0f;   // sum of U / sigma^2 (zero for bins t >= T)
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
             float w[M];
@@ -187,11 +237,14 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                 s2[m] = s;
                 w[m] = rcp(s);
             }
-            if (iter > 0 && valid[k]) {
-                float acc = 0.0f;
+            if (iter > 0) {
+                float l = 0.0f;
 #pragma unroll
-                for (int m = 0; m < M; ++m) acc += ln_fast(s2[m]) + U[k][m] * w[m];
-                llp += static_cast<double>(acc);
+                for (int m = 0; m < M; ++m) {
+                    l += log2_fast(s2[m]);
+                    uw = fmaf(U[k][m], w[m], uw);
+                }
+                lg2 = fmaf(mk[k], l, lg2);
             }
             if (!last) {
                 // Z_t = x_t x_t^H in Hermitian real parameters
@@ -216,23 +269,23 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                     for (int e = 0; e < M * M; ++e) q[m * M * M + e] = fmaf(w[m], z[e], q[m * M * M + e]);
             }
         }
-        // block reduction of Q (to wave 0) and of the LL partial
+        // row partials of Q and of the LL terms to LDS
         if (!last) {
 #pragma unroll
-            for (int i = 0; i < NQ; ++i) q[i] = wave_sum(q[i]);
+            for (int i = 0; i < NQ; ++i) q[i] = row_sum(q[i]);
         }
-        llp = wave_sum(llp);
-        if (lane == 0) {
+        double llp = row_sum(static_cast<double>(lg2) * static_cast<double>(kLn2f) + static_cast<double>(uw));
+        if (row_lead) {
             if (!last) {
 #pragma unroll
-                for (int i = 0; i < NQ; ++i) sm.red[buf][i][wid] = q[i];
+                for (int i = 0; i < NQ; ++i) sm.redq[i][row_slot] = q[i];
             }
-            sm.red_d[buf][wid] = llp;
+            sm.red_d[row_slot] = llp;
         }
         __syncthreads();
         if (wid == 0) {
             if (iter > 0) {
-                const double s = sum_slots(sm.red_d[buf]);
+                const double s = sum_slots<NR>(sm.red_d);
                 const double ll = ldet_prev - static_cast<double>(M) * kLnPi - s * invT;
                 if (lane == 0) it.ll_trace[iter - 1] = ll;
                 if (!(ll == ll) || ll == INFINITY || ll == -INFINITY) status = ST_NONFINITE;
@@ -240,15 +293,15 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
             if (!last && status == ST_OK) {
                 double ldet = 0.0;
                 if constexpr (M == 2) {
-                    // lane i sums value i over the wave slots, then every lane
+                    // lane i sums value i over the row slots, then every lane
                     // reads all eight sums from registers
                     double qs[8];
-                    const float mine = lane < 8 ? sum_slots(sm.red[buf][lane]) : 0.0f;
+                    const float mine = lane < 8 ? sum_slots<NR>(sm.redq[lane]) : 0.0f;
 #pragma unroll
                     for (int i = 0; i < 8; ++i) qs[i] = static_cast<double>(readlane_f(mine, i)) * invT;
                     status = ip_sweep_reg2(sm, qs, ldet);
                 } else {
-                    if (lane < NQ) sm.qtot[lane] = static_cast<double>(sum_slots(sm.red[buf][lane])) * invT;
+                    if (lane < NQ) sm.qtot[lane] = static_cast<double>(sum_slots<NR>(sm.redq[lane])) * invT;
                     __threadfence_block();
                     __builtin_amdgcn_wave_barrier();
                     // lane-parallel IP sweep in double precision
@@ -262,7 +315,6 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
         __syncthreads();
         status = sm.flag;
         if (status != ST_OK) break;
-        buf ^= 1;
 
         // ---------------- phase B: U = |P^H x|^2
         {
@@ -300,7 +352,7 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                     float s = 0.0f;
 #pragma unroll
                     for (int nn = 0; nn < N; ++nn) s = fmaf(vr[k][nn], lam[nn][m], s);
-                    const float is = valid[k] ? rcp(s) : 0.0f;
+                    const float is = mk[k] * rcp(s);
                     const float ua = U[k][m] * is * is;
 #pragma unroll
                     for (int n = 0; n < N; ++n) {
@@ -310,13 +362,13 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                 }
             }
 #pragma unroll
-            for (int i = 0; i < 2 * N * M; ++i) nd[i] = wave_sum(nd[i]);
-            if (lane == 0) {
+            for (int i = 0; i < 2 * N * M; ++i) nd[i] = wave_sum_last(nd[i]);
+            if (lane == 63) {
 #pragma unroll
-                for (int i = 0; i < 2 * N * M; ++i) sm.red[buf][i][wid] = nd[i];
+                for (int i = 0; i < 2 * N * M; ++i) sm.redc[buf][i][wid] = nd[i];
             }
             __syncthreads();
-            const float mine = lane < 2 * N * M ? sum_slots(sm.red[buf][lane]) : 0.0f;
+            const float mine = lane < 2 * N * M ? sum_slots<NW>(sm.redc[buf][lane]) : 0.0f;
             bool good = true;
 #pragma unroll
             for (int n = 0; n < N; ++n)
@@ -353,50 +405,59 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                     }
                 }
 #pragma unroll
-                for (int n = 0; n < N; ++n) vr[k][n] = valid[k] ? vr[k][n] * sqrtf(num[n] / den[n]) : 1.0f;
+                for (int n = 0; n < N; ++n) vr[k][n] = mk[k] != 0.0f ? vr[k][n] * sqrtf(num[n] / den[n]) : 1.0f;
             }
             continue;
         }
 
-        // ---------------- phase C (Algorithm 1): EM over sources, in order
+        // ---------------- phase C (Algorithm 1): EM over sources, in order.
+        // With g = h l / sigma^2 the posterior power of eq:Phidef divided by h is
+        //   e = l (1 + g (U / sigma^2 - 1)),
+        // so the L update is the T-mean of e and the H update is
+        //   h <- h * (1/M) sum_m e_m / l_new,m,
+        // which needs no reciprocal of h.
 #pragma unroll
         for (int n = 0; n < N; ++n) {
             if (status != ST_OK) continue;
             float part[M];
-            float phi[BPT][M];
+            float e[BPT][M];
+            float l2[M];
 #pragma unroll
-            for (int m = 0; m < M; ++m) part[m] = 0.0f;
+            for (int m = 0; m < M; ++m) {
+                part[m] = 0.0f;
+                l2[m] = lam[n][m] * lam[n][m];
+            }
 #pragma unroll
             for (int k = 0; k < BPT; ++k) {
-                const float rv = rcp(vr[k][n]);
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     float s = 0.0f;
 #pragma unroll
                     for (int nn = 0; nn < N; ++nn) s = fmaf(vr[k][nn], lam[nn][m], s);
-                    const float a = vr[k][n] * lam[n][m];
-                    const float g = a * rcp(s);
-                    const float ph = fmaf(g * g, U[k][m], (1.0f - g) * a);
-                    phi[k][m] = ph;
-                    part[m] += valid[k] ? ph * rv : 0.0f;
+                    const float w = rcp(s);
+                    const float r = fmaf(U[k][m], w, -1.0f);
+                    const float gl = (vr[k][n] * w) * l2[m];
+                    const float ek = fmaf(gl, r, lam[n][m]);
+                    e[k][m] = ek;
+                    part[m] = fmaf(mk[k], ek, part[m]);
                 }
             }
 #pragma unroll
-            for (int m = 0; m < M; ++m) part[m] = wave_sum(part[m]);
-            if (lane == 0) {
+            for (int m = 0; m < M; ++m) part[m] = wave_sum_last(part[m]);
+            if (lane == 63) {
 #pragma unroll
-                for (int m = 0; m < M; ++m) sm.red[buf][m][wid] = part[m];
+                for (int m = 0; m < M; ++m) sm.redc[buf][m][wid] = part[m];
             }
             __syncthreads();
-            float rl[M];
+            float c[M];
             bool good = true;
-            const float mine = lane < M ? sum_slots(sm.red[buf][lane]) : 0.0f;
+            const float mine = lane < M ? sum_slots<NW>(sm.redc[buf][lane]) : 0.0f;
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const float l = readlane_f(mine, m) * invTf;
                 good = good && (l > 0.0f) && (l < INFINITY);
                 lam[n][m] = l;
-                rl[m] = rcp(l);
+                c[m] = rcp(l * static_cast<float>(M));
             }
             buf ^= 1;
             if (!good) {
@@ -407,8 +468,8 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
             for (int k = 0; k < BPT; ++k) {
                 float s = 0.0f;
 #pragma unroll
-                for (int m = 0; m < M; ++m) s = fmaf(phi[k][m], rl[m], s);
-                vr[k][n] = valid[k] ? s * (1.0f / static_cast<float>(M)) : 1.0f;
+                for (int m = 0; m < M; ++m) s = fmaf(e[k][m], c[m], s);
+                vr[k][n] = mk[k] != 0.0f ? vr[k][n] * s : 1.0f;
             }
         }
         if (status != ST_OK) break;
@@ -418,7 +479,7 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {
         const int t = tid + k * nthr;
-        if (valid[k]) {
+        if (t < T) {
 #pragma unroll
             for (int n = 0; n < N; ++n) it.v[t * N + n] = vr[k][n];
         }

@@ -8,7 +8,7 @@ namespace ffca {
 // 128 (BPT 2), 256 (BPT 4) or 512 (BPT 8) VGPRs.
 template <int M, int N, int BPT>
 __global__ void __launch_bounds__(kResidentBins / BPT) em_kernel(EmLaunch a) {
-    __shared__ EmSmem sm;
+    __shared__ EmSmem<M * M * M, 2 * N * M, wave_slots(BPT)> sm;
     const WorkItem &it = a.items[blockIdx.x];
     if (*it.status != ST_OK) return;  // frozen after an earlier failure
     em_item<M, N, BPT>(it, a.n_iter, a.algo, sm);
@@ -61,7 +61,8 @@ bool em_supported(int M, int N, int bpt) { return em_lookup(M, N, bpt) != nullpt
 
 template <int BPT>
 __global__ void __launch_bounds__(kResidentBins / BPT) em_persistent_kernel(EmLaunch a) {
-    __shared__ EmSmem sm;
+    // widest reductions among the classes: Q_m of M = 4, 2NM of (4, 6)
+    __shared__ EmSmem<kRedW, 2 * 6 * 4, wave_slots(BPT)> sm;
     __shared__ int s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(a.queue, 1);
