@@ -106,63 +106,60 @@ __device__ __forceinline__ double sum_slots(const double *p) {
 }
 
 // IP sweep for M = 2 in registers (every lane of wave 0 computes the same
-// values): the 2 x 2 system of eq:ip1 is solved by its adjugate (Cramer's
-// rule), which for a 2 x 2 matrix is the elimination result without row
-// exchanges; the pivot test compares |det| with the largest entry squared.
-// qsum: the 8 reduced Hermitian parameters (Q_1 then Q_2), already / T.
+// values). For 2 x 2 matrices the solve of eq:ip1, w = (P^H Q_m)^{-1} e_m,
+// equals Q_m^{-1} P^{-H} e_m, and both inverses are adjugates over
+// determinants:
+//   P^{-H} e_m = b / conj(d),  d = det P,  b = conj(P11, -P01) (m = 1) or
+//                                          conj(-P10, P00) (m = 2);
+//   Q^{-1} = adj(Q) / det Q.
+// With u = adj(Q) b and s = b^H u, eq:ip2's normalization w^H Q w = 1 makes
+//   w = u d / sqrt(s det(Q) |d|^2),
+// one reciprocal square root per column and no division. The system is
+// taken as singular when |det(P^H Q)|^2 = |d|^2 det(Q)^2 falls below
+// tol^2 (|P|_F^2 |Q|_F^2)^2, the fourth power of a bound on its largest entry.
+// q: the 8 reduced Hermitian parameters (Q_1 then Q_2), already / T.
 template <class Smem>
 __device__ __forceinline__ int ip_sweep_reg2(Smem &sm, const double (&q)[8], double &ldet) {
-    cd P[2][2];
-    P[0][0] = ld(sm.Pd[0]);
-    P[0][1] = ld(sm.Pd[1]);
-    P[1][0] = ld(sm.Pd[2]);
-    P[1][1] = ld(sm.Pd[3]);
+    cd P00 = ld(sm.Pd[0]), P01 = ld(sm.Pd[1]), P10 = ld(sm.Pd[2]), P11 = ld(sm.Pd[3]);
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
         const double q00 = q[4 * m + 0], q11 = q[4 * m + 1];
         const cd q01 = cmk(q[4 * m + 2], q[4 * m + 3]);
         if (!(fabs(q00) < INFINITY) || !(fabs(q11) < INFINITY) || !(abs2(q01) < INFINITY))
             return ST_NONFINITE;
-        // A = P^H Q
-        cd A[2][2];
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const cd p0 = conjd(P[0][r]), p1 = conjd(P[1][r]);
-            A[r][0] = q00 * p0 + p1 * conjd(q01);
-            A[r][1] = p0 * q01 + q11 * p1;
-        }
-        const cd det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
-        const double d2 = abs2(det);
-        const double amax2 = fmax(fmax(abs2(A[0][0]), abs2(A[0][1])), fmax(abs2(A[1][0]), abs2(A[1][1])));
-        if (!(amax2 > 0.0) || !(amax2 < INFINITY) || !(d2 >= kPivotTol * kPivotTol * amax2 * amax2))
+        const cd b0 = m == 0 ? conjd(P11) : cmk(-P10.re, P10.im);
+        const cd b1 = m == 0 ? cmk(-P01.re, P01.im) : conjd(P00);
+        const cd u0 = q11 * b0 - q01 * b1;
+        const cd u1 = q00 * b1 - conjd(q01) * b0;
+        const double sb = (conjd(b0) * u0 + conjd(b1) * u1).re;
+        const double dq = q00 * q11 - abs2(q01);
+        const cd d = P00 * P11 - P01 * P10;
+        const double d2 = abs2(d);
+        const double nq = q00 * q00 + q11 * q11 + 2.0 * abs2(q01);
+        const double np = (abs2(P00) + abs2(P01)) + (abs2(P10) + abs2(P11));
+        const double t = sb * dq * d2;
+        if (!(d2 * dq * dq >= kPivotTol * kPivotTol * (np * nq) * (np * nq)) || !(t > 0.0) || !(t < INFINITY))
             return ST_SINGULAR;
-        // w = adj(A) e_m / det, with 1/det = conj(det) / |det|^2
-        const cd idet = rcp_d(d2) * conjd(det);
-        cd w0, w1;
+        const double r = rsqrt_d(t);
+        const cd w0 = r * (u0 * d), w1 = r * (u1 * d);
         if (m == 0) {
-            w0 = A[1][1] * idet;
-            w1 = cmk(-A[1][0].re, -A[1][0].im) * idet;
+            P00 = w0;
+            P10 = w1;
         } else {
-            w0 = cmk(-A[0][1].re, -A[0][1].im) * idet;
-            w1 = A[0][0] * idet;
+            P01 = w0;
+            P11 = w1;
         }
-        // normalization so that w^H Q w = 1
-        const double qq = q00 * abs2(w0) + q11 * abs2(w1) + 2.0 * (conjd(w0) * q01 * w1).re;
-        if (!(qq > 0.0) || !(qq < INFINITY)) return ST_SINGULAR;
-        const double inv = rsqrt_d(qq);
-        P[0][m] = inv * w0;
-        P[1][m] = inv * w1;
     }
     // ln|det P|^2 for the likelihood trace (single precision logarithm)
-    ldet = static_cast<double>(ln_fast(static_cast<float>(abs2(P[0][0] * P[1][1] - P[0][1] * P[1][0]))));
-    sm.Pd[0] = st(P[0][0]);
-    sm.Pd[1] = st(P[0][1]);
-    sm.Pd[2] = st(P[1][0]);
-    sm.Pd[3] = st(P[1][1]);
-    sm.P32[0] = make_float2(static_cast<float>(P[0][0].re), static_cast<float>(P[0][0].im));
-    sm.P32[1] = make_float2(static_cast<float>(P[0][1].re), static_cast<float>(P[0][1].im));
-    sm.P32[2] = make_float2(static_cast<float>(P[1][0].re), static_cast<float>(P[1][0].im));
-    sm.P32[3] = make_float2(static_cast<float>(P[1][1].re), static_cast<float>(P[1][1].im));
+    ldet = static_cast<double>(ln_fast(static_cast<float>(abs2(P00 * P11 - P01 * P10))));
+    sm.Pd[0] = st(P00);
+    sm.Pd[1] = st(P01);
+    sm.Pd[2] = st(P10);
+    sm.Pd[3] = st(P11);
+    sm.P32[0] = make_float2(static_cast<float>(P00.re), static_cast<float>(P00.im));
+    sm.P32[1] = make_float2(static_cast<float>(P01.re), static_cast<float>(P01.im));
+    sm.P32[2] = make_float2(static_cast<float>(P10.re), static_cast<float>(P10.im));
+    sm.P32[3] = make_float2(static_cast<float>(P11.re), static_cast<float>(P11.im));
     return ST_OK;
 }
 
