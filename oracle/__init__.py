@@ -10,6 +10,10 @@ Sec. IV-F (eq:Doclo) step by step in double precision.
 Arrays use the paper's roles with the library's layouts:
     x   [F,T,M] complex    P [F,M,M] complex (column m is w_m)
     lam [F,N,M] real       v [F,T,N] real      y [N,F,T,M] complex
+
+The ``*_blocks`` functions are the piecewise stationary extension (Sec. VI):
+blocks of B consecutive frames share h, the input of the algorithms is the
+block covariance Xhat_j, and v is [F,J,N] with J = T / B.
 """
 from __future__ import annotations
 
@@ -65,6 +69,18 @@ def _load():
         lib.ofc_mwf.argtypes = [c_int, c_int, c_int, c_int, vp, vp, vp, vp, vp]
         lib.ofc_mwf.restype = c_int
         lib.ofc_num_threads.restype = c_int
+        lib.ofc_block_cov.argtypes = [c_int, c_int, c_int, vp, vp]
+        lib.ofc_weighted_cov_blocks.argtypes = [c_int, c_int, c_int, vp, vp, vp, vp]
+        lib.ofc_block_power.argtypes = [c_int, c_int, vp, vp, vp]
+        lib.ofc_loglik_blocks_freq.argtypes = [c_int, c_int, c_int, vp, vp, vp, vp]
+        lib.ofc_loglik_blocks_freq.restype = c_double
+        lib.ofc_fit_blocks.argtypes = [c_int, c_int, c_int, c_int, c_int, vp, vp, vp, vp, c_int, c_int, vp,
+                                       c_int]
+        lib.ofc_fit_blocks.restype = c_int
+        lib.ofc_loglik_blocks.argtypes = [c_int, c_int, c_int, c_int, c_int, vp, vp, vp, vp, vp]
+        lib.ofc_loglik_blocks.restype = c_double
+        lib.ofc_mwf_blocks.argtypes = [c_int, c_int, c_int, c_int, c_int, vp, vp, vp, vp, vp]
+        lib.ofc_mwf_blocks.restype = c_int
         _lib = lib
     return _lib
 
@@ -201,4 +217,78 @@ def mwf(x, P, lam, v):
     st = _load().ofc_mwf(F, T, M, N, _p(x), _p(P), _p(lam), _p(v), _p(y))
     if st != OK:
         raise FloatingPointError("ofc_mwf status %d" % st)
+    return y
+
+
+# ---------------------------------------------------------------- piecewise stationary (Sec. VI)
+def block_cov(x, B):
+    """Xhat [J,M,M] = (1/B) sum_b x x^H over blocks of B frames of one frequency x [T,M]."""
+    x = _c128(x)
+    T, M = x.shape
+    J = T // B
+    Xh = np.zeros((J, M, M), np.complex128)
+    _load().ofc_block_cov(J, int(B), M, _p(x), _p(Xh))
+    return Xh
+
+
+def weighted_cov_blocks(Xh, lam, v):
+    """Q [M,M,M] = (1/J) sum_j Xhat_j / sigma^2_{mj} for one frequency."""
+    Xh, lam, v = _c128(Xh), _f64(lam), _f64(v)
+    J, M, _ = Xh.shape
+    N = lam.shape[0]
+    Q = np.zeros((M, M, M), np.complex128)
+    _load().ofc_weighted_cov_blocks(J, M, N, _p(Xh), _p(lam), _p(v), _p(Q))
+    return Q
+
+
+def block_power(P, Xh):
+    """U [M,J] = w_m^H Xhat_j w_m."""
+    P, Xh = _c128(P), _c128(Xh)
+    J, M, _ = Xh.shape
+    U = np.zeros((M, J), np.float64)
+    _load().ofc_block_power(J, M, _p(P), _p(Xh), _p(U))
+    return U
+
+
+def loglik_blocks_freq(Xh, P, lam, v):
+    """Block-model LL per frame of one frequency (eq:negllpws, sign flipped, /J, M ln pi restored)."""
+    Xh, P, lam, v = _c128(Xh), _c128(P), _f64(lam), _f64(v)
+    J, M, _ = Xh.shape
+    N = lam.shape[0]
+    return float(_load().ofc_loglik_blocks_freq(J, M, N, _p(Xh), _p(P), _p(lam), _p(v)))
+
+
+def fit_blocks(x, B, P, lam, v, n_iter, algo=0, trace=False, nthreads=0):
+    """fit() for the block model: v [F,J,N]. Returns (P, lam, v, ll_trace)."""
+    x = _c128(x)
+    P, lam, v = _c128(P).copy(), _f64(lam).copy(), _f64(v).copy()
+    F, T, M = x.shape
+    N = lam.shape[1]
+    tr = np.zeros((F, max(n_iter, 1)), np.float64) if trace else None
+    st = _load().ofc_fit_blocks(F, T, M, N, int(B), _p(x), _p(P), _p(lam), _p(v), int(n_iter), int(algo),
+                                _p(tr) if trace else None, int(nthreads))
+    if st != OK:
+        raise FloatingPointError("ofc_fit_blocks status %d" % st)
+    return P, lam, v, (tr[:, :n_iter].mean(axis=0) if trace else None)
+
+
+def loglik_blocks(x, B, P, lam, v):
+    """(LL per frame, per-frequency LL [F]) of the block model."""
+    x, P, lam, v = _c128(x), _c128(P), _f64(lam), _f64(v)
+    F, T, M = x.shape
+    N = lam.shape[1]
+    llf = np.zeros(F, np.float64)
+    ll = _load().ofc_loglik_blocks(F, T, M, N, int(B), _p(x), _p(P), _p(lam), _p(v), _p(llf))
+    return float(ll), llf
+
+
+def mwf_blocks(x, B, P, lam, v):
+    """Source images y [N,F,T,M] of the block model (each frame uses its block's h)."""
+    x, P, lam, v = _c128(x), _c128(P), _f64(lam), _f64(v)
+    F, T, M = x.shape
+    N = lam.shape[1]
+    y = np.zeros((N, F, T, M), np.complex128)
+    st = _load().ofc_mwf_blocks(F, T, M, N, int(B), _p(x), _p(P), _p(lam), _p(v), _p(y))
+    if st != OK:
+        raise FloatingPointError("ofc_mwf_blocks status %d" % st)
     return y

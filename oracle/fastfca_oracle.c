@@ -513,6 +513,244 @@ int ofc_mwf(int F, int T, int M, int N, const cplx *x, const cplx *P,
     return OFC_OK;
 }
 
+/* ------------------------------------------------------------------------
+ * Piecewise stationary extension (Sec. VI, "Piecewise Stationary Extension
+ * of FastFCA"). Frames are partitioned into J = T / B blocks of B consecutive
+ * frames; within block j every frame has the covariance
+ * sum_n h_{jn} P^{-H} Lambda_n P^{-1}. The cost eq:negllpws is minimized by
+ * the same Algorithm 1 / Algorithm 2 with the input Xhat_j = (1/B) sum_b
+ * x_j^(b) x_j^(b)H in place of x_j x_j^H, so that
+ *   Q_m = (1/J) sum_j Xhat_j / sigma^2_{mj},  U_{mj} = w_m^H Xhat_j w_m
+ * (the short-term power <|y_mj|^2>), and v is [J][N].
+ * Layout: Xh [J][M][M] complex per frequency, [F][J][M][M] for all.
+ * ------------------------------------------------------------------------ */
+
+/* Xhat_j = (1/B) sum_{b<B} x_{jB+b} x_{jB+b}^H for one frequency; x [T][M], T = J B. */
+void ofc_block_cov(int J, int B, int M, const cplx *x, cplx *Xh)
+{
+    for (int j = 0; j < J; ++j) {
+        cplx *Xj = Xh + (size_t)j * M * M;
+        for (int i = 0; i < M * M; ++i)
+            Xj[i] = 0.0;
+        for (int b = 0; b < B; ++b) {
+            const cplx *xt = x + ((size_t)j * B + b) * M;
+            for (int r = 0; r < M; ++r)
+                for (int c = 0; c < M; ++c)
+                    Xj[r * M + c] += xt[r] * conj(xt[c]);
+        }
+        for (int i = 0; i < M * M; ++i)
+            Xj[i] /= (double)B;
+    }
+}
+
+/* Q_m = (1/J) sum_j Xhat_j / sigma^2_{mj}, all m (eq:wsampcov with Xhat_j). */
+void ofc_weighted_cov_blocks(int J, int M, int N, const cplx *Xh, const double *lam,
+                             const double *v, cplx *Q)
+{
+    memset(Q, 0, sizeof(cplx) * (size_t)M * M * M);
+    for (int j = 0; j < J; ++j) {
+        const cplx *Xj = Xh + (size_t)j * M * M;
+        const double *vj = v + (size_t)j * N;
+        for (int m = 0; m < M; ++m) {
+            double w = 1.0 / sigma2_at(M, N, lam, vj, m);
+            cplx *Qm = Q + (size_t)m * M * M;
+            for (int i = 0; i < M * M; ++i)
+                Qm[i] += w * Xj[i];
+        }
+    }
+    for (int i = 0; i < M * M * M; ++i)
+        Q[i] /= (double)J;
+}
+
+/* U_{mj} = w_m^H Xhat_j w_m, the short-term power of y_m in block j. U [M][J]. */
+void ofc_block_power(int J, int M, const cplx *P, const cplx *Xh, double *U)
+{
+    for (int j = 0; j < J; ++j) {
+        const cplx *Xj = Xh + (size_t)j * M * M;
+        for (int m = 0; m < M; ++m) {
+            cplx q = 0.0;
+            for (int r = 0; r < M; ++r) {
+                cplx s = 0.0;
+                for (int c = 0; c < M; ++c)
+                    s += Xj[r * M + c] * P[c * M + m];
+                q += conj(P[r * M + m]) * s;
+            }
+            U[(size_t)m * J + j] = creal(q);
+        }
+    }
+}
+
+/*
+ * Per-frequency log-likelihood per frame of the piecewise stationary model:
+ * minus eq:negllpws divided by J, with M ln(pi) restored,
+ *   LL_f = ln|det P|^2 - (1/J) sum_{m,j} [ ln pi + ln sigma^2_{mj} + U_{mj}/sigma^2_{mj} ].
+ */
+double ofc_loglik_blocks_freq(int J, int M, int N, const cplx *Xh, const cplx *P,
+                              const double *lam, const double *v)
+{
+    const double lnpi = log(3.14159265358979323846);
+    double *U = (double *)malloc(sizeof(double) * (size_t)M * J);
+    if (!U)
+        return NAN;
+    ofc_block_power(J, M, P, Xh, U);
+    double acc = 0.0;
+    for (int j = 0; j < J; ++j)
+        for (int m = 0; m < M; ++m) {
+            double s2 = sigma2_at(M, N, lam, v + (size_t)j * N, m);
+            acc += lnpi + log(s2) + U[(size_t)m * J + j] / s2;
+        }
+    free(U);
+    return ofc_logabsdet2(M, P) - acc / (double)J;
+}
+
+/* One iteration of the block model on one frequency (what, algo as in
+ * ofc_iterate_freq). Qwork: M*M*M complex; dwork: 3*M*J doubles. */
+int ofc_iterate_blocks_freq(int J, int M, int N, const cplx *Xh, cplx *P, double *lam,
+                            double *v, int what, int algo, cplx *Qwork, double *dwork)
+{
+    if (what & 1) {
+        ofc_weighted_cov_blocks(J, M, N, Xh, lam, v, Qwork);
+        for (int m = 0; m < M; ++m) {
+            int st = ofc_ip_column(M, P, Qwork + (size_t)m * M * M, m);
+            if (st != OFC_OK)
+                return st;
+        }
+    }
+    if (what & 2) {
+        double *U = dwork;
+        double *scratch = dwork + (size_t)M * J;
+        ofc_block_power(J, M, P, Xh, U);
+        if (algo == 0) {
+            for (int n = 0; n < N; ++n)
+                ofc_em_source(J, M, N, U, lam, v, n, scratch);
+        } else {
+            ofc_mm_update(J, M, N, U, lam, v, scratch);
+        }
+    }
+    return OFC_OK;
+}
+
+/*
+ * Fit the block model on all F frequencies: x [F][T][M] with T = J B,
+ * P [F][M][M], lam [F][N][M], v [F][J][N]; ll_trace [F][n_iter] or NULL.
+ */
+int ofc_fit_blocks(int F, int T, int M, int N, int B, const cplx *x, cplx *P, double *lam,
+                   double *v, int n_iter, int algo, double *ll_trace, int nthreads)
+{
+    if (F < 1 || B < 1 || T < B || T % B != 0 || M < 1 || M > 64 || N < 1 || n_iter < 0)
+        return OFC_E_ARG;
+    const int J = T / B;
+    int status = OFC_OK;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        cplx *Xh = (cplx *)malloc(sizeof(cplx) * (size_t)J * M * M);
+        cplx *Qw = (cplx *)malloc(sizeof(cplx) * (size_t)M * M * M);
+        double *dw = (double *)malloc(sizeof(double) * 3 * (size_t)M * J);
+#pragma omp for schedule(dynamic, 1)
+        for (int f = 0; f < F; ++f) {
+            if (!Xh || !Qw || !dw) {
+#pragma omp critical
+                status = OFC_E_NOMEM;
+                continue;
+            }
+            ofc_block_cov(J, B, M, x + (size_t)f * T * M, Xh);
+            cplx *Pf = P + (size_t)f * M * M;
+            double *lf = lam + (size_t)f * N * M;
+            double *vf = v + (size_t)f * J * N;
+            for (int it = 0; it < n_iter; ++it) {
+                int st = ofc_iterate_blocks_freq(J, M, N, Xh, Pf, lf, vf, 3, algo, Qw, dw);
+                if (st != OFC_OK) {
+#pragma omp critical
+                    if (status == OFC_OK)
+                        status = st;
+                    break;
+                }
+                if (ll_trace)
+                    ll_trace[(size_t)f * n_iter + it] = ofc_loglik_blocks_freq(J, M, N, Xh, Pf, lf, vf);
+            }
+        }
+        free(Xh);
+        free(Qw);
+        free(dw);
+    }
+    return status;
+}
+
+/* Mean over f of the block-model LL per frame (ll_f [F] optional). */
+double ofc_loglik_blocks(int F, int T, int M, int N, int B, const cplx *x, const cplx *P,
+                         const double *lam, const double *v, double *ll_f)
+{
+    if (B < 1 || T % B != 0)
+        return NAN;
+    const int J = T / B;
+    cplx *Xh = (cplx *)malloc(sizeof(cplx) * (size_t)J * M * M);
+    if (!Xh)
+        return NAN;
+    double acc = 0.0;
+    for (int f = 0; f < F; ++f) {
+        ofc_block_cov(J, B, M, x + (size_t)f * T * M, Xh);
+        double l = ofc_loglik_blocks_freq(J, M, N, Xh, P + (size_t)f * M * M, lam + (size_t)f * N * M,
+                                          v + (size_t)f * J * N);
+        if (ll_f)
+            ll_f[f] = l;
+        acc += l;
+    }
+    free(Xh);
+    return acc / (double)F;
+}
+
+/*
+ * Multichannel Wiener filter of the block model (eq:Doclo applied to every
+ * frame, with the block's h): y_{n,t} = P^{-H} diag_m(h_{jn} lam_{nm} /
+ * sigma^2_{mj}) P^H x_t, j = t / B. v [F][J][N]; y [N][F][T][M].
+ */
+int ofc_mwf_blocks(int F, int T, int M, int N, int B, const cplx *x, const cplx *P,
+                   const double *lam, const double *v, cplx *y)
+{
+    if (M < 1 || M > 64 || B < 1 || T % B != 0)
+        return OFC_E_ARG;
+    const int J = T / B;
+    for (int f = 0; f < F; ++f) {
+        const cplx *Pf = P + (size_t)f * M * M;
+        const double *lf = lam + (size_t)f * N * M;
+        cplx Pinv[64 * 64];
+        if (invert(M, Pf, Pinv) != OFC_OK)
+            return OFC_E_SINGULAR;
+        for (int t = 0; t < T; ++t) {
+            const cplx *xt = x + ((size_t)f * T + t) * M;
+            const double *vj = v + ((size_t)f * J + t / B) * N;
+            cplx z[64];
+            for (int m = 0; m < M; ++m) {
+                cplx s = 0.0;
+                for (int r = 0; r < M; ++r)
+                    s += conj(Pf[r * M + m]) * xt[r];
+                z[m] = s;
+            }
+            for (int n = 0; n < N; ++n) {
+                cplx *yn = y + (((size_t)n * F + f) * T + t) * M;
+                cplx gz[64];
+                for (int m = 0; m < M; ++m) {
+                    double s2 = sigma2_at(M, N, lf, vj, m);
+                    gz[m] = (vj[n] * lf[n * M + m] / s2) * z[m];
+                }
+                for (int r = 0; r < M; ++r) {
+                    cplx s = 0.0;
+                    for (int c = 0; c < M; ++c)
+                        s += conj(Pinv[c * M + r]) * gz[c];
+                    yn[r] = s;
+                }
+            }
+        }
+    }
+    return OFC_OK;
+}
+
 int ofc_num_threads(void)
 {
 #ifdef _OPENMP

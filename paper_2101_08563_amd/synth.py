@@ -76,6 +76,21 @@ def init_params(x, N, config_id=0, mixture_id=0):
     return P, lam, v
 
 
+def init_params_blocks(x, N, B, config_id=0, mixture_id=0):
+    """Initial state of the piecewise stationary model (blocks of B frames):
+    as init_params with the frame power replaced by the block's mean power;
+    v is [F, T//B, N]."""
+    F, T, M = x.shape
+    J = T // B
+    rng = _rng(config_id, mixture_id, 4)
+    p = (np.abs(x[:, :J * B].astype(np.complex128)) ** 2).sum(axis=2).reshape(F, J, B).mean(axis=2) / (M * N)
+    d = 1e-6 * p.mean(axis=1, keepdims=True)
+    lam = (0.5 + rng.random((F, N, M))).astype(np.float32)
+    v = ((p + d)[..., None] * (0.5 + rng.random((F, J, N)))).astype(np.float32)
+    P = np.broadcast_to(np.eye(M, dtype=np.complex128), (F, M, M)).copy()
+    return P, lam, v
+
+
 def batch_specs(B=256, F=513, config_id=2, seed=0):
     """Shapes of the mixed batch: T ~ U{200..2000}, M in {2,3,4}, N in {M+1, M+2}."""
     rng = _rng(config_id, 10**6 + seed, 2)
