@@ -108,6 +108,27 @@ int fastfca_init_batch(fastfca_ctx **out, int B, const fastfca_problem *probs,
                        uint64_t seed, void *hip_stream);
 
 /*
+ * fastfca_init_blocks -- a context holding one mixture fitted with the
+ * piecewise stationary model (Sec. VI, eq:negllpws): the T frames of x are
+ * split into J = T / block_len blocks of block_len consecutive frames that
+ * share the source powers h, and Algorithms 1 and 2 run on the block
+ * covariances Xhat_j = (1/block_len) sum_b x x^H in place of x_t x_t^H
+ * (Q_m = (1/J) sum_j Xhat_j / sigma^2_mj, U_mj = w_m^H Xhat_j w_m).
+ * T must be a positive multiple of block_len and J >= M; block_len = 1
+ * gives the frame model through this path. v0 (and the v of get/set_params)
+ * is [F][J][N]; fastfca_shape reports T = J; fastfca_mwf writes all T
+ * frames, each with its block's h. Runs the on-chip kernels: M <= 4, N <= 8,
+ * J <= 2048 (E_UNSUPPORTED otherwise). Otherwise as fastfca_init.
+ */
+int fastfca_init_blocks(fastfca_ctx **out, const fastfca_c64 *x, int F, int T, int M, int N,
+                        int block_len, const fastfca_c128 *P0, const float *lambda0,
+                        const float *v0, uint64_t seed, void *hip_stream);
+
+/* Frames per block of mixture b of a fastfca_init_blocks context; 0 for a
+ * frame context; E_ARG for a bad index. */
+int fastfca_block_length(const fastfca_ctx *c, int b);
+
+/*
  * fastfca_em_step -- run n_iter >= 1 iterations of Algorithm 1 (IP sweep over
  * m = 1..M using eq:wsampcov, eq:ip1, eq:ip2; U by eq:Udef; EM update of
  * L[:,n] then H[n,:] for n = 1..N in order) on every frequency of every

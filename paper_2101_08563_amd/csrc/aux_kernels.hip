@@ -111,6 +111,33 @@ __global__ void __launch_bounds__(kAuxThreads) loglik_kernel(const WorkItem *ite
     __syncthreads();
     double acc = 0.0;
     for (int t = tid; t < T; t += blockDim.x) {
+        const float *vt = it.v + static_cast<size_t>(t) * N;
+        if (it.z) {
+            // block model (Sec. VI): U_mj = w_m^H Xhat_j w_m, Xhat_j from its
+            // Hermitian parameters
+            const float *zt = it.z + static_cast<size_t>(t) * M * M;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                double u = 0.0;
+                int p = M;
+#pragma unroll
+                for (int r = 0; r < M; ++r) {
+                    const double2 a = Ps[r * M + m];
+                    u += (a.x * a.x + a.y * a.y) * static_cast<double>(zt[r]);
+#pragma unroll
+                    for (int c = r + 1; c < M; ++c) {
+                        const double2 b = Ps[c * M + m];
+                        u += 2.0 * ((a.x * b.x + a.y * b.y) * static_cast<double>(zt[p]) -
+                                    (a.x * b.y - a.y * b.x) * static_cast<double>(zt[p + 1]));
+                        p += 2;
+                    }
+                }
+                double s2 = 0.0;
+                for (int n = 0; n < N; ++n) s2 += static_cast<double>(vt[n]) * lam_s[n * M + m];
+                acc += kLnPiD + log(s2) + u / s2;
+            }
+            continue;
+        }
         double xr[M], xi[M];
 #pragma unroll
         for (int r = 0; r < M; ++r) {
@@ -118,7 +145,6 @@ __global__ void __launch_bounds__(kAuxThreads) loglik_kernel(const WorkItem *ite
             xr[r] = v.x;
             xi[r] = v.y;
         }
-        const float *vt = it.v + static_cast<size_t>(t) * N;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             double yr = 0.0, yi = 0.0;
@@ -145,7 +171,8 @@ __global__ void __launch_bounds__(kAuxThreads) loglik_kernel(const WorkItem *ite
 }
 
 // ------------------------------------------------------------------ MWF (eq:Doclo)
-// Grid (ceil(T / blockDim), F). One thread per TF bin:
+// Grid (ceil(Tx / blockDim), F). One thread per TF bin (frame t; its h is
+// that of block t / B):
 //   z = P^H x ;  for each n: y_n = B (g_n .* z),  g_nm = h_n lam_nm / sigma^2_m,
 // with B = P^{-H} from pinv_kernel.
 template <int M>
@@ -157,7 +184,7 @@ __global__ void __launch_bounds__(kAuxThreads) mwf_kernel(const WorkItem *items,
     const int f = blockIdx.y;
     const WorkItem &it = items[f];
     const int tid = threadIdx.x;
-    const int T = it.T, N = it.N;
+    const int T = it.Tx, N = it.N;
     if (tid < M * M) {
         const double2 p = it.P[tid];
         Ps[tid] = make_float2(static_cast<float>(p.x), static_cast<float>(p.y));
@@ -183,7 +210,7 @@ __global__ void __launch_bounds__(kAuxThreads) mwf_kernel(const WorkItem *items,
         }
         z[m] = make_float2(zr, zi);
     }
-    const float *vt = it.v + static_cast<size_t>(t) * N;
+    const float *vt = it.v + static_cast<size_t>(t / it.B) * N;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         float s = 0.f;
@@ -262,9 +289,9 @@ __device__ __forceinline__ double unif24(uint64_t seed, uint64_t k) {
 
 // One workgroup per frequency. lambda_nm = 0.5 + u;
 // v_tn = (|x_t|^2/(MN) + d_f)(0.5 + u'), d_f = 1e-6 mean_t |x_t|^2/(MN).
-__global__ void __launch_bounds__(kAuxThreads) seeded_init_kernel(const float2 *x, float *lam,
-                                                                  float *v, int T, int M, int N,
-                                                                  uint64_t seed, int do_lam,
+__global__ void __launch_bounds__(kAuxThreads) seeded_init_kernel(const float2 *x, const float *z,
+                                                                  float *lam, float *v, int T, int M,
+                                                                  int N, uint64_t seed, int do_lam,
                                                                   int do_v) {
     __shared__ double red[kAuxThreads / 64];
     const int f = blockIdx.x;
@@ -277,15 +304,22 @@ __global__ void __launch_bounds__(kAuxThreads) seeded_init_kernel(const float2 *
     }
     if (!do_v) return;
     const float2 *xf = x + static_cast<size_t>(f) * T * M;
-    double acc = 0.0;
-    for (int t = tid; t < T; t += blockDim.x) {
+    const float *zf = z ? z + static_cast<size_t>(f) * T * M * M : nullptr;
+    // power of bin t: |x_t|^2, or tr(Xhat_t) for a block
+    auto power = [&](int t) {
         double p = 0.0;
         for (int r = 0; r < M; ++r) {
-            const float2 e = xf[static_cast<size_t>(t) * M + r];
-            p += static_cast<double>(e.x) * e.x + static_cast<double>(e.y) * e.y;
+            if (zf) {
+                p += static_cast<double>(zf[static_cast<size_t>(t) * M * M + r]);
+            } else {
+                const float2 e = xf[static_cast<size_t>(t) * M + r];
+                p += static_cast<double>(e.x) * e.x + static_cast<double>(e.y) * e.y;
+            }
         }
-        acc += p * inv_mn;
-    }
+        return p;
+    };
+    double acc = 0.0;
+    for (int t = tid; t < T; t += blockDim.x) acc += power(t) * inv_mn;
     acc = wave_sum(acc);
     if ((tid & 63) == 0) red[tid >> 6] = acc;
     __syncthreads();
@@ -293,12 +327,7 @@ __global__ void __launch_bounds__(kAuxThreads) seeded_init_kernel(const float2 *
     for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) tot += red[w];
     const double d = 1e-6 * tot / static_cast<double>(T);
     for (int t = tid; t < T; t += blockDim.x) {
-        double p = 0.0;
-        for (int r = 0; r < M; ++r) {
-            const float2 e = xf[static_cast<size_t>(t) * M + r];
-            p += static_cast<double>(e.x) * e.x + static_cast<double>(e.y) * e.y;
-        }
-        p *= inv_mn;
+        const double p = power(t) * inv_mn;
         for (int n = 0; n < N; ++n) {
             const uint64_t k = (1ULL << 40) + (static_cast<uint64_t>(f) * T + t) * N + n;
             v[(static_cast<size_t>(f) * T + t) * N + n] =
@@ -375,10 +404,51 @@ hipError_t launch_fill_int(int *p, int n, int value, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_seeded_init(const float2 *x, float *lam, float *v, int F, int T, int M, int N,
-                              uint64_t seed, bool do_lam, bool do_v, hipStream_t s) {
-    hipLaunchKernelGGL(seeded_init_kernel, dim3(F), dim3(kAuxThreads), 0, s, x, lam, v, T, M, N,
+hipError_t launch_seeded_init(const float2 *x, const float *z, float *lam, float *v, int F, int T,
+                              int M, int N, uint64_t seed, bool do_lam, bool do_v, hipStream_t s) {
+    hipLaunchKernelGGL(seeded_init_kernel, dim3(F), dim3(kAuxThreads), 0, s, x, z, lam, v, T, M, N,
                        seed, do_lam ? 1 : 0, do_v ? 1 : 0);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ block covariances
+// Xhat_j = (1/B) sum_b x_{jB+b} x_{jB+b}^H (Sec. VI) as M^2 real parameters:
+// the diagonal, then re/im of the upper triangle in row-major order. One
+// thread per (block, frequency); double precision accumulation.
+__global__ void block_cov_kernel(const float2 *x, float *z, int J, int B, int M) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int f = blockIdx.y;
+    if (j >= J) return;
+    const float2 *xb = x + (static_cast<size_t>(f) * J + j) * B * M;
+    float *zo = z + (static_cast<size_t>(f) * J + j) * M * M;
+    const double inv = 1.0 / static_cast<double>(B);
+    for (int r = 0; r < M; ++r) {
+        double d = 0.0;
+        for (int b = 0; b < B; ++b) {
+            const float2 a = xb[static_cast<size_t>(b) * M + r];
+            d += static_cast<double>(a.x) * a.x + static_cast<double>(a.y) * a.y;
+        }
+        zo[r] = static_cast<float>(d * inv);
+    }
+    int p = M;
+    for (int r = 0; r < M; ++r)
+        for (int c = r + 1; c < M; ++c) {
+            double re = 0.0, im = 0.0;
+            for (int b = 0; b < B; ++b) {
+                const float2 a = xb[static_cast<size_t>(b) * M + r], e = xb[static_cast<size_t>(b) * M + c];
+                // x_r conj(x_c)
+                re += static_cast<double>(a.x) * e.x + static_cast<double>(a.y) * e.y;
+                im += static_cast<double>(a.y) * e.x - static_cast<double>(a.x) * e.y;
+            }
+            zo[p] = static_cast<float>(re * inv);
+            zo[p + 1] = static_cast<float>(im * inv);
+            p += 2;
+        }
+}
+
+hipError_t launch_block_cov(const float2 *x, float *z, int F, int J, int B, int M, hipStream_t s) {
+    dim3 grid((J + 127) / 128, F);
+    hipLaunchKernelGGL(block_cov_kernel, grid, dim3(128), 0, s, x, z, J, B, M);
     return hipGetLastError();
 }
 

@@ -163,9 +163,14 @@ __device__ __forceinline__ int ip_sweep_reg2(Smem &sm, const double (&q)[8], dou
     return ST_OK;
 }
 
-template <int M, int N, int BPT, class Smem>
+// COV = false: every bin is one frame and its statistics come from x_t.
+// COV = true: every bin is a block of the piecewise stationary model (Sec. VI)
+// whose block covariance Xhat_j (M^2 real parameters, read from it.z) replaces
+// x_j x_j^H: Q_m takes Xhat_j / sigma^2 and U_mj = w_m^H Xhat_j w_m.
+template <int M, int N, int BPT, bool COV, class Smem>
 __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo, Smem &sm) {
     constexpr int NQ = M * M * M;
+    constexpr int M2 = M * M;
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
     constexpr int NR = Smem::kRowSlots;
@@ -180,7 +185,8 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
 
     // ---- load the frequency's state. Bins t >= T hold x = 0 and h = 1: they
     // add nothing to Q or U, and mk = 0 drops them from the other sums.
-    float2 xr[BPT][M];
+    float2 xr[BPT][COV ? 1 : M];
+    float zr[BPT][COV ? M2 : 1];
     float vr[BPT][N];
     float U[BPT][M];
     float mk[BPT];
@@ -189,8 +195,13 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
         const int t = tid + k * nthr;
         const bool valid = t < T;
         mk[k] = valid ? 1.0f : 0.0f;
+        if constexpr (COV) {
 #pragma unroll
-        for (int r = 0; r < M; ++r) xr[k][r] = valid ? it.x[t * M + r] : make_float2(0.f, 0.f);
+            for (int e = 0; e < M2; ++e) zr[k][e] = valid ? it.z[t * M2 + e] : 0.0f;
+        } else {
+#pragma unroll
+            for (int r = 0; r < M; ++r) xr[k][r] = valid ? it.x[t * M + r] : make_float2(0.f, 0.f);
+        }
 #pragma unroll
         for (int n = 0; n < N; ++n) vr[k][n] = valid ? it.v[t * N + n] : 1.0f;
 #pragma unroll
@@ -244,12 +255,15 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                 lg2 = fmaf(mk[k], l, lg2);
             }
             if (!last) {
-                // Z_t = x_t x_t^H in Hermitian real parameters
+                // Z_t = x_t x_t^H (or Xhat_j) in Hermitian real parameters
                 float z[M * M];
+                if constexpr (COV) {
 #pragma unroll
-                for (int r = 0; r < M; ++r)
-                    z[r] = xr[k][r].x * xr[k][r].x + xr[k][r].y * xr[k][r].y;
-                {
+                    for (int e = 0; e < M2; ++e) z[e] = zr[k][e];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < M; ++r)
+                        z[r] = xr[k][r].x * xr[k][r].x + xr[k][r].y * xr[k][r].y;
                     int p = M;
 #pragma unroll
                     for (int r = 0; r < M; ++r)
@@ -313,8 +327,39 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
         status = sm.flag;
         if (status != ST_OK) break;
 
-        // ---------------- phase B: U = |P^H x|^2
-        {
+        // ---------------- phase B: U = |P^H x|^2, or w_m^H Xhat w_m
+        if constexpr (COV) {
+            // U_m = sum_e c_m[e] z[e]: |P_rm|^2 on the diagonal parameters,
+            // 2 Re and -2 Im of conj(P_rm) P_cm on those of entry (r, c), r < c
+            float cm[M][M2];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+#pragma unroll
+                for (int r = 0; r < M; ++r) {
+                    const float2 a = sm.P32[r * M + m];
+                    cm[m][r] = a.x * a.x + a.y * a.y;
+                }
+                int p = M;
+#pragma unroll
+                for (int r = 0; r < M; ++r)
+#pragma unroll
+                    for (int c = r + 1; c < M; ++c) {
+                        const float2 a = sm.P32[r * M + m], b = sm.P32[c * M + m];
+                        cm[m][p] = 2.0f * (a.x * b.x + a.y * b.y);
+                        cm[m][p + 1] = -2.0f * (a.x * b.y - a.y * b.x);
+                        p += 2;
+                    }
+            }
+#pragma unroll
+            for (int k = 0; k < BPT; ++k)
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    float u = 0.0f;
+#pragma unroll
+                    for (int e = 0; e < M2; ++e) u = fmaf(cm[m][e], zr[k][e], u);
+                    U[k][m] = fmaxf(u, 0.0f);
+                }
+        } else {
             float2 Pw[M][M];
 #pragma unroll
             for (int i = 0; i < M * M; ++i) Pw[i / M][i % M] = sm.P32[i];

@@ -11,11 +11,10 @@ __global__ void __launch_bounds__(kResidentBins / BPT) em_kernel(EmLaunch a) {
     __shared__ EmSmem<M * M * M, 2 * N * M, wave_slots(BPT)> sm;
     const WorkItem &it = a.items[blockIdx.x];
     if (*it.status != ST_OK) return;  // frozen after an earlier failure
-    em_item<M, N, BPT>(it, a.n_iter, a.algo, sm);
+    em_item<M, N, BPT, false>(it, a.n_iter, a.algo, sm);
 }
 
 // ------------------------------------------------------------------ dispatch
-using EmFn = void (*)(EmLaunch);
 
 template <int M, int N>
 struct BptTable {
@@ -51,7 +50,9 @@ static EmFn em_lookup(int M, int N, int bpt) {
     }
 }
 
-bool em_supported(int M, int N, int bpt) { return em_lookup(M, N, bpt) != nullptr; }
+bool em_supported(int M, int N, int bpt, bool cov) {
+    return (cov ? em_cov_lookup(M, N, bpt) : em_lookup(M, N, bpt)) != nullptr;
+}
 
 // Persistent launch over a mixed batch: every workgroup pulls the next work
 // item (one frequency of one mixture, longest first) from a device counter
@@ -74,7 +75,7 @@ __global__ void __launch_bounds__(kResidentBins / BPT) em_persistent_kernel(EmLa
         if (*it.status != ST_OK) continue;
         switch (it.M * 16 + it.N) {
 #define FFCA_CASE(MM, NN) \
-    case MM * 16 + NN: em_item<MM, NN, BPT>(it, a.n_iter, a.algo, sm); break;
+    case MM * 16 + NN: em_item<MM, NN, BPT, false>(it, a.n_iter, a.algo, sm); break;
             FFCA_PERSISTENT_CLASSES(FFCA_CASE)
 #undef FFCA_CASE
             default: break;
@@ -137,8 +138,8 @@ hipError_t launch_em_wide(int M, int N, int bpt, int threads, const EmLaunch &a,
 }
 
 hipError_t launch_em(int M, int N, int bpt, int threads, const EmLaunch &a, int grid,
-                     hipStream_t s) {
-    EmFn fn = em_lookup(M, N, bpt);
+                     hipStream_t s, bool cov) {
+    EmFn fn = cov ? em_cov_lookup(M, N, bpt) : em_lookup(M, N, bpt);
     if (!fn) return hipErrorInvalidValue;
     if (threads < 64 || threads * bpt > kResidentBins || (threads & 63)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(threads), 0, s, a);

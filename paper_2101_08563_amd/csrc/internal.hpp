@@ -10,14 +10,19 @@ namespace ffca {
 // One unit of GPU work: one frequency of one mixture. Every array pointer
 // addresses that frequency's slice in the library's own buffers.
 struct WorkItem {
-    const float2 *x;   // [T][M]  mixture STFT
-    float *v;          // [T][N]  source powers h_{tn}
+    const float2 *x;   // [Tx][M] mixture STFT frames
+    const float *z;    // [T][M*M] block covariances of the piecewise stationary
+                       // model (diagonal, then re/im of the upper triangle), or
+                       // nullptr when every bin is one frame (z_t = x_t x_t^H)
+    float *v;          // [T][N]  source powers h_{tn} (one per bin or block)
     float *lam;        // [N][M]  diag(Lambda_n)
     double2 *P;        // [M][M]  decorrelation matrix, double precision master
     double *ll_trace;  // [trace_stride] LL per bin after each iteration
     double *ldet;      // ln|det P|^2 after the last IP sweep
     int *status;       // 0 = ok, else FASTFCA_E_* recorded by the kernel
-    int T, M, N;
+    int T, M, N;       // T: bins the iteration runs over (frames, or blocks)
+    int B;             // frames per bin: 1, or the block length
+    int Tx;            // frames in x (T * B)
     int cls;           // kernel class index (M, N) used by the persistent launch
 };
 
@@ -45,9 +50,12 @@ struct EmLaunch {
 
 // Launch one EM kernel (Algorithm 1 for n_iter iterations) over `n_items`
 // work items that share (M, N). bpt: bins per thread held in registers.
+// cov: the items carry block covariances (piecewise stationary model).
 hipError_t launch_em(int M, int N, int bpt, int threads, const EmLaunch &a, int grid,
-                     hipStream_t s);
-bool em_supported(int M, int N, int bpt);
+                     hipStream_t s, bool cov = false);
+bool em_supported(int M, int N, int bpt, bool cov = false);
+using EmFn = void (*)(EmLaunch);
+EmFn em_cov_lookup(int M, int N, int bpt);
 
 // Wide family (M <= 8, N <= 12, T <= kWideBins = 4096): x is re-read from
 // global memory each iteration; see em_wide.hpp. One lookup per M, defined in
@@ -77,8 +85,11 @@ hipError_t launch_mwf(const WorkItem *items, int F, int T, int M, int N, float2 
 hipError_t launch_check_finite_x(const float2 *x, size_t n, int *flag, hipStream_t s);
 hipError_t launch_check_positive(const float *a, size_t n, int *flag, hipStream_t s);
 hipError_t launch_identity_P(double2 *P, int F, int M, hipStream_t s);
-hipError_t launch_seeded_init(const float2 *x, float *lam, float *v, int F, int T, int M,
-                              int N, uint64_t seed, bool do_lam, bool do_v, hipStream_t s);
+// v from the frame power |x_t|^2 or, when z is given, from the block power tr(Xhat_j).
+hipError_t launch_seeded_init(const float2 *x, const float *z, float *lam, float *v, int F, int T,
+                              int M, int N, uint64_t seed, bool do_lam, bool do_v, hipStream_t s);
+// Block covariances z [F][J][M*M] of x [F][J*B][M] (Sec. VI).
+hipError_t launch_block_cov(const float2 *x, float *z, int F, int J, int B, int M, hipStream_t s);
 hipError_t launch_fill_int(int *p, int n, int value, hipStream_t s);
 
 }  // namespace ffca

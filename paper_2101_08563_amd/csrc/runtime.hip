@@ -34,8 +34,11 @@ namespace {
 thread_local std::string g_init_error;
 
 struct Problem {
-    int F = 0, T = 0, M = 0, N = 0;
-    float2 *x = nullptr;
+    int F = 0, T = 0, M = 0, N = 0;  // T: bins of the iteration (frames, or blocks)
+    int B = 1;                       // frames per block (piecewise stationary model)
+    bool blocks = false;             // bins are blocks with covariances in z
+    float2 *x = nullptr;             // [F][T*B][M]
+    float *z = nullptr;              // [F][T][M*M] block covariances (blocks only)
     float *v = nullptr;
     float *lam = nullptr;
     double2 *P = nullptr;
@@ -48,6 +51,7 @@ struct Problem {
 
 struct ClassCfg {
     int M, N, Tmax;
+    bool cov = false;   // bins carry block covariances (piecewise stationary model)
     bool wide = false;  // wide family (x re-read per iteration) instead of resident
     int threads = 0, bpt = 0;
     std::vector<int> items;  // item indices of this class, in launch order
@@ -116,6 +120,7 @@ int dalloc(fastfca_ctx *c, T **p, size_t count) {
 
 void free_problem(Problem &p) {
     hipFree(p.x);
+    hipFree(p.z);
     hipFree(p.v);
     hipFree(p.lam);
     hipFree(p.P);
@@ -163,6 +168,10 @@ bool use_resident(int M, int N, int Tmax) {
 
 // Default launch shape of a class.
 bool pick_class(ClassCfg &cc) {
+    if (cc.cov) {  // block model: resident family only
+        cc.wide = false;
+        return use_resident(cc.M, cc.N, cc.Tmax) && pick_default(cc.Tmax, cc.threads, cc.bpt);
+    }
     cc.wide = !use_resident(cc.M, cc.N, cc.Tmax);
     if (!cc.wide) return pick_default(cc.Tmax, cc.threads, cc.bpt);
     cc.bpt = 8;
@@ -188,12 +197,13 @@ int build_items(fastfca_ctx *c) {
     std::map<std::pair<int, int>, int> cls_of;
     c->classes.clear();
     for (auto &p : c->probs) {
-        auto key = std::make_pair(p.M, p.N);
+        auto key = std::make_pair(p.M, p.N + (p.blocks ? 1000 : 0));
         if (!cls_of.count(key)) {
             cls_of[key] = static_cast<int>(c->classes.size());
             ClassCfg cc;
             cc.M = p.M;
             cc.N = p.N;
+            cc.cov = p.blocks;
             cc.Tmax = 0;
             c->classes.push_back(cc);
         }
@@ -208,10 +218,13 @@ int build_items(fastfca_ctx *c) {
     c->h_items.assign(total, WorkItem{});
     for (size_t b = 0; b < c->probs.size(); ++b) {
         auto &p = c->probs[b];
-        const int cls = cls_of[std::make_pair(p.M, p.N)];
+        const int cls = cls_of[std::make_pair(p.M, p.N + (p.blocks ? 1000 : 0))];
         for (int f = 0; f < p.F; ++f) {
             WorkItem w{};
-            w.x = p.x + static_cast<size_t>(f) * p.T * p.M;
+            w.x = p.x + static_cast<size_t>(f) * p.T * p.B * p.M;
+            w.z = p.blocks ? p.z + static_cast<size_t>(f) * p.T * p.M * p.M : nullptr;
+            w.B = p.B;
+            w.Tx = p.T * p.B;
             w.v = p.v + static_cast<size_t>(f) * p.T * p.N;
             w.lam = p.lam + static_cast<size_t>(f) * p.N * p.M;
             w.P = p.P + static_cast<size_t>(f) * p.M * p.M;
@@ -231,8 +244,9 @@ int build_items(fastfca_ctx *c) {
         });
     for (auto &cc : c->classes) {
         if (!pick_class(cc))
-            return set_err(c, FASTFCA_E_UNSUPPORTED, "no compiled kernel for M=%d N=%d T=%d", cc.M,
-                           cc.N, cc.Tmax);
+            return set_err(c, FASTFCA_E_UNSUPPORTED, "no compiled kernel for M=%d N=%d T=%d%s", cc.M,
+                           cc.N, cc.Tmax,
+                           cc.cov ? " (the block model runs M<=4, N<=8, at most 2048 blocks)" : "");
     }
     int rc;
     if ((rc = dalloc(c, &c->d_status, total)) != FASTFCA_OK) return rc;
@@ -304,7 +318,8 @@ int upload_items(fastfca_ctx *c, int n_iter) {
 int alloc_problem(fastfca_ctx *c, Problem &p) {
     int rc;
     const size_t F = p.F, T = p.T, M = p.M, N = p.N;
-    if ((rc = dalloc(c, &p.x, F * T * M)) != FASTFCA_OK) return rc;
+    if ((rc = dalloc(c, &p.x, F * T * p.B * M)) != FASTFCA_OK) return rc;
+    if (p.blocks && (rc = dalloc(c, &p.z, F * T * M * M)) != FASTFCA_OK) return rc;
     if ((rc = dalloc(c, &p.v, F * T * N)) != FASTFCA_OK) return rc;
     if ((rc = dalloc(c, &p.lam, F * N * M)) != FASTFCA_OK) return rc;
     if ((rc = dalloc(c, &p.P, F * M * M)) != FASTFCA_OK) return rc;
@@ -315,15 +330,15 @@ int alloc_problem(fastfca_ctx *c, Problem &p) {
 }
 
 int init_problem(fastfca_ctx *c, Problem &p, const fastfca_problem &d, uint64_t seed, int b) {
-    const size_t F = p.F, T = p.T, M = p.M, N = p.N;
-    HIPCHK(c, hipMemcpyAsync(p.x, d.x, sizeof(float2) * F * T * M, hipMemcpyDeviceToDevice,
+    const size_t F = p.F, T = p.T, M = p.M, N = p.N, Tx = static_cast<size_t>(p.T) * p.B;
+    HIPCHK(c, hipMemcpyAsync(p.x, d.x, sizeof(float2) * F * Tx * M, hipMemcpyDeviceToDevice,
                              c->stream));
     int *flag = nullptr;
     int rc = dalloc(c, &flag, 3);
     if (rc != FASTFCA_OK) return rc;
     int hflag[3] = {0, 0, 0};
     hipError_t e = hipMemcpyAsync(flag, hflag, sizeof hflag, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = launch_check_finite_x(p.x, F * T * M, flag, c->stream);
+    if (e == hipSuccess) e = launch_check_finite_x(p.x, F * Tx * M, flag, c->stream);
     if (e == hipSuccess && d.lambda0) e = launch_check_positive(d.lambda0, F * N * M, flag + 1, c->stream);
     if (e == hipSuccess && d.v0) e = launch_check_positive(d.v0, F * T * N, flag + 2, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, c->stream);
@@ -344,19 +359,29 @@ int init_problem(fastfca_ctx *c, Problem &p, const fastfca_problem &d, uint64_t 
     if (d.v0)
         HIPCHK(c, hipMemcpyAsync(p.v, d.v0, sizeof(float) * F * T * N, hipMemcpyDeviceToDevice,
                                  c->stream));
+    if (p.blocks) HIPCHK(c, launch_block_cov(p.x, p.z, p.F, p.T, p.B, p.M, c->stream));
     if (!d.lambda0 || !d.v0)
-        HIPCHK(c, launch_seeded_init(p.x, p.lam, p.v, p.F, p.T, p.M, p.N, seed, !d.lambda0, !d.v0,
+        HIPCHK(c, launch_seeded_init(p.x, p.z, p.lam, p.v, p.F, p.T, p.M, p.N, seed, !d.lambda0, !d.v0,
                                      c->stream));
     return FASTFCA_OK;
 }
 
-int create(fastfca_ctx **out, int B, const fastfca_problem *probs, uint64_t seed, void *stream) {
+// block_len > 0: one mixture fitted with the piecewise stationary model,
+// blocks of block_len frames (probs[0].T frames in x).
+int create(fastfca_ctx **out, int B, const fastfca_problem *probs, uint64_t seed, void *stream,
+           int block_len = 0) {
     if (!out) return set_err(nullptr, FASTFCA_E_ARG, "out is NULL");
     *out = nullptr;
     if (B < 1 || !probs) return set_err(nullptr, FASTFCA_E_ARG, "need B >= 1 problems");
+    if (block_len > 0) {
+        if (B != 1) return set_err(nullptr, FASTFCA_E_ARG, "the block model takes one mixture");
+        if (probs[0].T < block_len || probs[0].T % block_len != 0)
+            return set_err(nullptr, FASTFCA_E_ARG, "T=%d frames is not a positive multiple of the block length %d",
+                           probs[0].T, block_len);
+    }
     for (int b = 0; b < B; ++b) {
         const auto &d = probs[b];
-        int rc = validate_shape(nullptr, d.F, d.T, d.M, d.N);
+        int rc = validate_shape(nullptr, d.F, block_len > 0 ? d.T / block_len : d.T, d.M, d.N);
         if (rc != FASTFCA_OK) {
             g_init_error = "mixture " + std::to_string(b) + ": " + g_init_error;
             return rc;
@@ -377,6 +402,11 @@ int create(fastfca_ctx **out, int B, const fastfca_problem *probs, uint64_t seed
         p.T = probs[b].T;
         p.M = probs[b].M;
         p.N = probs[b].N;
+        if (block_len > 0) {
+            p.blocks = true;
+            p.B = block_len;
+            p.T = probs[b].T / block_len;
+        }
         rc = alloc_problem(c, p);
         if (rc == FASTFCA_OK) rc = init_problem(c, p, probs[b], seed + static_cast<uint64_t>(b), b);
     }
@@ -430,7 +460,7 @@ int record_em(fastfca_ctx *c, int n_iter) {
                                      static_cast<int>(cc.items.size()), c->stream));
         else
             HIPCHK(c, launch_em(cc.M, cc.N, cc.bpt, cc.threads, a, static_cast<int>(cc.items.size()),
-                                c->stream));
+                                c->stream, cc.cov));
     }
     return FASTFCA_OK;
 }
@@ -471,6 +501,19 @@ int fastfca_init(fastfca_ctx **out, const fastfca_c64 *x, int F, int T, int M, i
 int fastfca_init_batch(fastfca_ctx **out, int B, const fastfca_problem *probs, uint64_t seed,
                        void *hip_stream) {
     return create(out, B, probs, seed, hip_stream);
+}
+
+int fastfca_init_blocks(fastfca_ctx **out, const fastfca_c64 *x, int F, int T, int M, int N,
+                        int block_len, const fastfca_c128 *P0, const float *lambda0, const float *v0,
+                        uint64_t seed, void *hip_stream) {
+    if (block_len < 1) return set_err(nullptr, FASTFCA_E_ARG, "block length must be >= 1");
+    fastfca_problem d{x, F, T, M, N, P0, lambda0, v0};
+    return create(out, 1, &d, seed, hip_stream, block_len);
+}
+
+int fastfca_block_length(const fastfca_ctx *c, int b) {
+    if (!c || b < 0 || b >= static_cast<int>(c->probs.size())) return FASTFCA_E_ARG;
+    return c->probs[b].blocks ? c->probs[b].B : 0;
 }
 
 int fastfca_em_step(fastfca_ctx *c, int n_iter) {
@@ -565,7 +608,7 @@ int fastfca_mwf(fastfca_ctx *c, int b, fastfca_c64 *y) {
     if (!valid_problem(c, b) || !y) return c ? set_err(c, FASTFCA_E_ARG, "bad arguments") : FASTFCA_E_ARG;
     auto &p = c->probs[b];
     HIPCHK(c, launch_pinv(p.items, p.F, p.M, p.Bh, p.ldet, c->stream));
-    HIPCHK(c, launch_mwf_bins(p.items, p.Bh, p.F, p.T, p.M, reinterpret_cast<float2 *>(y), c->stream));
+    HIPCHK(c, launch_mwf_bins(p.items, p.Bh, p.F, p.T * p.B, p.M, reinterpret_cast<float2 *>(y), c->stream));
     return FASTFCA_OK;
 }
 
@@ -621,6 +664,9 @@ int fastfca_set_config(fastfca_ctx *c, int threads, int bins_per_thread) {
         if (threads * bins_per_thread < cc.Tmax)
             return set_err(c, FASTFCA_E_ARG, "threads*bins_per_thread=%d < T=%d",
                            threads * bins_per_thread, cc.Tmax);
+        if (!cc.wide && !em_supported(cc.M, cc.N, bins_per_thread, cc.cov))
+            return set_err(c, FASTFCA_E_ARG, "no kernel with %d bins per thread for M=%d N=%d",
+                           bins_per_thread, cc.M, cc.N);
         if (!cc.wide && threads * bins_per_thread > kResidentBins)
             return set_err(c, FASTFCA_E_ARG, "threads*bins_per_thread=%d > 2048 for M=%d N=%d",
                            threads * bins_per_thread, cc.M, cc.N);
@@ -666,7 +712,7 @@ int fastfca_get_config(const fastfca_ctx *c, int b, int *threads, int *bins_per_
     }
     const auto &p = c->probs[b];
     for (const auto &cc : c->classes)
-        if (cc.M == p.M && cc.N == p.N) {
+        if (cc.M == p.M && cc.N == p.N && cc.cov == p.blocks) {
             if (threads) *threads = cc.threads;
             if (bins_per_thread) *bins_per_thread = cc.bpt;
             return FASTFCA_OK;
@@ -786,7 +832,7 @@ int fastfca_autotune(fastfca_ctx *c, int n_iter, const char *cache_path) {
             for (int bpt : {2, 4, 8, 16}) {
                 const int th = threads_for(cc.Tmax, bpt, cc.wide ? kWideMaxT : kResidentBins);
                 if (!th) continue;
-                if (cc.wide ? !em_wide_supported(cc.M, cc.N, bpt) : !em_supported(cc.M, cc.N, bpt))
+                if (cc.wide ? !em_wide_supported(cc.M, cc.N, bpt) : !em_supported(cc.M, cc.N, bpt, cc.cov))
                     continue;
                 cc.threads = th;
                 cc.bpt = bpt;

@@ -39,6 +39,8 @@ SIGNATURES = {
     "fastfca_autotune": (_i, [_vp, _i, ctypes.c_char_p]),
     "fastfca_get_config": (_i, [_vp, _i, _pi, _pi]),
     "fastfca_set_algorithm": (_i, [_vp, _i]),
+    "fastfca_init_blocks": (_i, [ctypes.POINTER(_vp), _vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _u64, _vp]),
+    "fastfca_block_length": (_i, [_vp, _i]),
     "fastfca_synth_mixture": (_i, [_vp, _i, _i, _i, _i, _i, ctypes.c_float, _u64, _vp]),
     "fastfca_last_error": (ctypes.c_char_p, [_vp]),
     "fastfca_destroy": (None, [_vp]),
@@ -147,6 +149,26 @@ class FastFCA:
         self._ctx = ctx
 
     @classmethod
+    def from_blocks(cls, x, N, block_len, P0=None, lam0=None, v0=None, seed=0, stream=None):
+        """Piecewise stationary model (Sec. VI): blocks of block_len frames of
+        x [F,T,M] share h, so v0 (and get_params' v) is [F, T // block_len, N];
+        mwf() still returns every frame."""
+        lib = load_library()
+        stream = stream if stream is not None else torch.cuda.current_stream()
+        F, T, M = x.shape
+        J = T // block_len
+        _check_dev(x, torch.complex64, (F, T, M), "x")
+        _check_dev(P0, torch.complex128, (F, M, M), "P0")
+        _check_dev(lam0, torch.float32, (F, N, M), "lam0")
+        _check_dev(v0, torch.float32, (F, J, N), "v0")
+        ctx = ctypes.c_void_p()
+        rc = lib.fastfca_init_blocks(ctypes.byref(ctx), _ptr(x), F, T, M, int(N), int(block_len), _ptr(P0),
+                                     _ptr(lam0), _ptr(v0), int(seed), _stream(stream))
+        if rc != OK:
+            raise FastFCAError(rc, lib.fastfca_last_error(None).decode())
+        return cls(stream=stream, _ctx=ctx)
+
+    @classmethod
     def from_batch(cls, problems, seed=0, stream=None):
         """problems: list of dicts with x [F,T,M] and N, optional P0, lam0, v0."""
         lib = load_library()
@@ -203,8 +225,13 @@ class FastFCA:
         n = self._chk(self._lib.fastfca_ll_trace(self._ctx, b, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(buf)))
         return buf[:n].copy()
 
+    def block_length(self, b=0):
+        """Frames per block of the piecewise stationary model, 0 for the frame model."""
+        return self._chk(self._lib.fastfca_block_length(self._ctx, b))
+
     def mwf(self, b=0, out=None):
         F, T, M, N = self.shape(b)
+        T *= max(1, self.block_length(b))
         y = out if out is not None else torch.empty((N, F, T, M), dtype=torch.complex64, device="cuda")
         _check_dev(y, torch.complex64, (N, F, T, M), "y")
         self._chk(self._lib.fastfca_mwf(self._ctx, b, _ptr(y)))

@@ -1,0 +1,116 @@
+"""GPU parity of the piecewise stationary model (Sec. VI) against the FP64
+oracle: blocks of B frames share h, the iterations run on the block
+covariances (fastfca_init_blocks). Same bars as the frame model: normwise
+1e-4 on v, lambda, P and every y_n, 1e-6 nats per frame on the LL."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2101_08563_amd import FastFCA, FastFCAError, synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+REL_TOL = 1e-4
+LL_TOL = 1e-6
+
+
+def rel(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+
+
+def dev(*arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in arrs]
+
+
+def case(F, T, M, N, B, cid):
+    x = synth.mixture(F=F, T=T, M=M, N=N, rank=4, diffuse=0.1, config_id=cid, mixture_id=B)
+    P0, lam0, v0 = synth.init_params_blocks(x, N, B, config_id=cid, mixture_id=B)
+    return x, P0, lam0, v0
+
+
+@pytest.mark.parametrize("M,N,B,T,algo", [(2, 3, 4, 1000, 0), (3, 4, 8, 1600, 0), (4, 6, 5, 1000, 0),
+                                          (2, 2, 3, 231, 0), (2, 3, 4, 1000, 1), (3, 5, 2, 770, 1)])
+def test_block_model_parity(M, N, B, T, algo):
+    F, iters = 9, 25
+    x, P0, lam0, v0 = case(F, T, M, N, B, 60 + M)
+    xd, Pd, ld, vd = dev(x, P0, lam0, v0)
+    ctx = FastFCA.from_blocks(xd, N, B, Pd, ld, vd)
+    assert ctx.block_length() == B and ctx.shape()[1] == T // B
+    if algo:
+        ctx.set_algorithm("mm")
+    ctx.em_step(iters)
+    ctx.sync()
+    trace = ctx.ll_trace()
+    ll = ctx.loglik()
+    P, lam, v = (t.cpu().numpy() for t in ctx.get_params())
+    y = ctx.mwf().cpu().numpy()
+    ctx.close()
+    Po, lo, vo, tro = oracle.fit_blocks(x, B, P0, lam0, v0, iters, algo=algo, trace=True)
+    llo, _ = oracle.loglik_blocks(x, B, Po, lo, vo)
+    yo = oracle.mwf_blocks(x, B, Po, lo, vo)
+    errs = dict(v=rel(v, vo), lam=rel(lam, lo), P=rel(P, Po), ll=abs(ll - llo),
+                y=max(rel(y[n], yo[n]) for n in range(N)), trace=float(np.abs(trace - tro).max()))
+    print("blocks M%d N%d B%d T%d algo%d" % (M, N, B, T, algo), errs, flush=True)
+    assert errs["v"] < REL_TOL and errs["lam"] < REL_TOL and errs["P"] < REL_TOL, errs
+    assert errs["y"] < REL_TOL and errs["ll"] < LL_TOL and errs["trace"] < 1e-4, errs
+    assert np.diff(trace).min() > -1e-5
+
+
+def test_block_length_one_matches_frame_context():
+    x, P0, lam0, v0 = case(7, 500, 2, 3, 1, 66)
+    xd, Pd, ld, vd = dev(x, P0, lam0, v0)
+    a = FastFCA(xd, 3, Pd, ld, vd)
+    b = FastFCA.from_blocks(xd, 3, 1, Pd, ld, vd)
+    for c in (a, b):
+        c.em_step(20)
+        c.sync()
+    pa = [t.cpu().numpy() for t in a.get_params()]
+    pb = [t.cpu().numpy() for t in b.get_params()]
+    for u, w in zip(pa, pb):
+        assert rel(w, u) < 2e-5
+    assert abs(a.loglik() - b.loglik()) < 1e-6
+    a.close()
+    b.close()
+
+
+def test_block_seeded_init_uses_block_power():
+    """Library-side init: lambda as for frames; v from tr(Xhat_j)/(MN) with the
+    SplitMix64 counter stream of the frame model over (f, j, n)."""
+    x, _, _, _ = case(3, 120, 2, 3, 4, 67)
+    F, T, M = x.shape
+    N, B, seed = 3, 4, 77
+    J = T // B
+    ctx = FastFCA.from_blocks(*dev(x), N, B, seed=seed)
+    _, lam, v = (t.cpu().numpy() for t in ctx.get_params())
+    ctx.close()
+    mask = (1 << 64) - 1
+
+    def u(k):
+        z = (seed + (k + 1) * 0x9E3779B97F4A7C15) & mask
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask
+        z ^= z >> 31
+        return (z >> 40) / 16777216.0
+
+    p = (np.abs(x.astype(np.complex128)) ** 2).sum(axis=2).reshape(F, J, B).mean(axis=2) / (M * N)
+    d = 1e-6 * p.mean(axis=1)
+    v_ref = np.array([[[(p[f, j] + d[f]) * (0.5 + u((1 << 40) + (f * J + j) * N + n)) for n in range(N)]
+                       for j in range(J)] for f in range(F)])
+    assert np.abs(v - v_ref).max() <= 1e-6 * np.abs(v_ref).max()
+    assert lam.min() >= 0.5 and lam.max() < 1.5
+
+
+def test_block_errors():
+    x, _, _, _ = case(2, 100, 2, 3, 3, 68)
+    with pytest.raises(FastFCAError) as e:
+        FastFCA.from_blocks(*dev(x), 3, 3)          # 100 frames is not a multiple of 3
+    assert e.value.code == -1
+    with pytest.raises(FastFCAError) as e:
+        FastFCA.from_blocks(*dev(x), 3, 100)        # J = 1 < M
+    assert e.value.code == -1
+    x5 = synth.mixture(F=2, T=60, M=5, N=6, config_id=69)
+    with pytest.raises(FastFCAError) as e:
+        FastFCA.from_blocks(*dev(x5), 6, 2)         # the block model runs M <= 4
+    assert e.value.code == -7
