@@ -244,6 +244,7 @@ def bench_batch(args):
     stream.synchronize()
     probs = [dict(x=x, N=s["N"]) for x, s in zip(xs, specs)]
     batch = FastFCA.from_batch(probs, seed=1, stream=stream)
+    batch.autotune(n_iter=10)  # launch shape and persistent grid (state is restored)
     batch.em_step(2)
     batch.sync()
     t_batch = _time(lambda: batch.em_step(iters), stream, max(2, args.steps // 5))

@@ -11,6 +11,9 @@ Arrays use the paper's roles with the library's layouts:
     x   [F,T,M] complex    P [F,M,M] complex (column m is w_m)
     lam [F,N,M] real       v [F,T,N] real      y [N,F,T,M] complex
 
+The ``mnmf_*`` functions are FastMNMF (Sec. V and its appendix): h_{ijn} =
+sum_k t_{ikn} v_{jkn} with tp [I,K,N] and va [J,K,N].
+
 The ``*_blocks`` functions are the piecewise stationary extension (Sec. VI):
 blocks of B consecutive frames share h, the input of the algorithms is the
 block covariance Xhat_j, and v is [F,J,N] with J = T / B.
@@ -81,6 +84,13 @@ def _load():
         lib.ofc_loglik_blocks.restype = c_double
         lib.ofc_mwf_blocks.argtypes = [c_int, c_int, c_int, c_int, c_int, vp, vp, vp, vp, vp]
         lib.ofc_mwf_blocks.restype = c_int
+        lib.ofc_mnmf_h.argtypes = [c_int, c_int, c_int, c_int, vp, vp, vp]
+        lib.ofc_mnmf_loglik.argtypes = [c_int, c_int, c_int, c_int, c_int, vp, vp, vp, vp, vp, vp]
+        lib.ofc_mnmf_loglik.restype = c_double
+        lib.ofc_mnmf_iterate.argtypes = [c_int, c_int, c_int, c_int, c_int, vp, vp, vp, vp, vp, c_int]
+        lib.ofc_mnmf_iterate.restype = c_int
+        lib.ofc_mnmf_fit.argtypes = [c_int, c_int, c_int, c_int, c_int, vp, vp, vp, vp, vp, c_int, vp]
+        lib.ofc_mnmf_fit.restype = c_int
         _lib = lib
     return _lib
 
@@ -292,3 +302,53 @@ def mwf_blocks(x, B, P, lam, v):
     if st != OK:
         raise FloatingPointError("ofc_mwf_blocks status %d" % st)
     return y
+
+
+# ---------------------------------------------------------------- FastMNMF (Sec. V, appendix)
+def mnmf_h(tp, va):
+    """h [I,J,N] = sum_k t_{ikn} v_{jkn}."""
+    tp, va = _f64(tp), _f64(va)
+    I, K, N = tp.shape
+    J = va.shape[0]
+    h = np.zeros((I, J, N), np.float64)
+    _load().ofc_mnmf_h(I, J, N, K, _p(tp), _p(va), _p(h))
+    return h
+
+
+def mnmf_loglik(x, P, lam, tp, va):
+    """(LL per bin, per-frequency LL [I]) of FastMNMF (eq:FastMNMFcost)."""
+    x, P, lam, tp, va = _c128(x), _c128(P), _f64(lam), _f64(tp), _f64(va)
+    I, J, M = x.shape
+    N = lam.shape[1]
+    K = tp.shape[1]
+    llf = np.zeros(I, np.float64)
+    ll = _load().ofc_mnmf_loglik(I, J, M, N, K, _p(x), _p(P), _p(lam), _p(tp), _p(va), _p(llf))
+    return float(ll), llf
+
+
+def mnmf_iterate(x, P, lam, tp, va, what=15):
+    """One FastMNMF iteration (bit 0 IP, 1 Lambda, 2 T, 3 V). Returns copies (P, lam, tp, va)."""
+    x = _c128(x)
+    P, lam, tp, va = _c128(P).copy(), _f64(lam).copy(), _f64(tp).copy(), _f64(va).copy()
+    I, J, M = x.shape
+    N = lam.shape[1]
+    K = tp.shape[1]
+    st = _load().ofc_mnmf_iterate(I, J, M, N, K, _p(x), _p(P), _p(lam), _p(tp), _p(va), int(what))
+    if st != OK:
+        raise FloatingPointError("ofc_mnmf_iterate status %d" % st)
+    return P, lam, tp, va
+
+
+def mnmf_fit(x, P, lam, tp, va, n_iter, trace=False):
+    """n_iter FastMNMF iterations. Returns (P, lam, tp, va, ll_trace or None)."""
+    x = _c128(x)
+    P, lam, tp, va = _c128(P).copy(), _f64(lam).copy(), _f64(tp).copy(), _f64(va).copy()
+    I, J, M = x.shape
+    N = lam.shape[1]
+    K = tp.shape[1]
+    tr = np.zeros(max(n_iter, 1), np.float64) if trace else None
+    st = _load().ofc_mnmf_fit(I, J, M, N, K, _p(x), _p(P), _p(lam), _p(tp), _p(va), int(n_iter),
+                              _p(tr) if trace else None)
+    if st != OK:
+        raise FloatingPointError("ofc_mnmf_fit status %d" % st)
+    return P, lam, tp, va, (tr[:n_iter] if trace else None)

@@ -751,6 +751,180 @@ int ofc_mwf_blocks(int F, int T, int M, int N, int B, const cplx *x, const cplx 
     return OFC_OK;
 }
 
+/* ------------------------------------------------------------------------
+ * FastMNMF (Sec. V, "FastMNMF: Full-band Extension of FastFCA"; appendix
+ * "FastMNMF", eq:NMFconst2, eq:FastMNMFcost). The source powers are no
+ * longer free: h_{ijn} = sum_k t_{ikn} v_{jkn}, with spectral patterns T_n
+ * shared over frames and activations V_n shared over frequencies, so the
+ * frequencies are coupled through V. The cost is eq:negll summed over
+ * frequencies with that h. W_i is updated by IP (eq:ip1, eq:ip2) as in
+ * FastFCA, and Lambda, T, V by majorization-minimization of the
+ * Itakura-Saito part sum (U/sigma^2 + ln sigma^2): for a parameter theta
+ * entering sigma^2_b = theta phi_b + (rest), the auxiliary function built from
+ * the convexity of 1/sigma^2 and the concavity of ln sigma^2 is minimized by
+ *   theta <- theta * sqrt( sum_b phi_b U_b / sigma_b^4 / sum_b phi_b / sigma_b^2 )
+ * with sigma^2 from the current values. One iteration: IP for every i, U,
+ * then Lambda, then T, then V, each from the latest values of the others.
+ * Layouts (F frequencies i, T frames j): x [F][T][M], P [F][M][M],
+ * lam [F][N][M], tp [F][K][N] (t_{ikn}), va [T][K][N] (v_{jkn}); h [F][T][N].
+ * ------------------------------------------------------------------------ */
+
+/* h_{ijn} = sum_k t_{ikn} v_{jkn} (eq:NMFconst2). */
+void ofc_mnmf_h(int F, int T, int N, int K, const double *tp, const double *va, double *h)
+{
+    for (int i = 0; i < F; ++i)
+        for (int j = 0; j < T; ++j)
+            for (int n = 0; n < N; ++n) {
+                double s = 0.0;
+                for (int k = 0; k < K; ++k)
+                    s += tp[((size_t)i * K + k) * N + n] * va[((size_t)j * K + k) * N + n];
+                h[((size_t)i * T + j) * N + n] = s;
+            }
+}
+
+/* LL per bin averaged over frequencies (eq:FastMNMFcost, sign flipped,
+ * divided by F T, M ln pi restored); ll_f [F] optional. */
+double ofc_mnmf_loglik(int F, int T, int M, int N, int K, const cplx *x, const cplx *P,
+                       const double *lam, const double *tp, const double *va, double *ll_f)
+{
+    double *h = (double *)malloc(sizeof(double) * (size_t)F * T * N);
+    if (!h)
+        return NAN;
+    ofc_mnmf_h(F, T, N, K, tp, va, h);
+    double acc = 0.0;
+    for (int i = 0; i < F; ++i) {
+        double l = ofc_loglik_freq(T, M, N, x + (size_t)i * T * M, P + (size_t)i * M * M,
+                                   lam + (size_t)i * N * M, h + (size_t)i * T * N);
+        if (ll_f)
+            ll_f[i] = l;
+        acc += l;
+    }
+    free(h);
+    return acc / (double)F;
+}
+
+/*
+ * One FastMNMF iteration over all frequencies. what: bit 0 = IP sweep of
+ * every W_i, bit 1 = Lambda, bit 2 = T, bit 3 = V (in that order).
+ * Returns OFC_OK or the first IP failure.
+ */
+int ofc_mnmf_iterate(int F, int T, int M, int N, int K, const cplx *x, cplx *P, double *lam,
+                     double *tp, double *va, int what)
+{
+    const size_t FT = (size_t)F * T;
+    double *h = (double *)malloc(sizeof(double) * FT * N);
+    double *U = (double *)malloc(sizeof(double) * FT * M);      /* [F][M][T] */
+    double *s2 = (double *)malloc(sizeof(double) * FT * M);     /* [F][T][M] */
+    cplx *Q = (cplx *)malloc(sizeof(cplx) * (size_t)M * M * M);
+    double *num = (double *)malloc(sizeof(double) * (size_t)T * K * N);
+    double *den = (double *)malloc(sizeof(double) * (size_t)T * K * N);
+    int status = OFC_OK;
+    if (!h || !U || !s2 || !Q || !num || !den) {
+        status = OFC_E_NOMEM;
+        goto done;
+    }
+#define SIG2()                                                                             \
+    do {                                                                                   \
+        ofc_mnmf_h(F, T, N, K, tp, va, h);                                                 \
+        for (int i = 0; i < F; ++i)                                                        \
+            for (int j = 0; j < T; ++j)                                                    \
+                for (int m = 0; m < M; ++m)                                                \
+                    s2[((size_t)i * T + j) * M + m] =                                      \
+                        sigma2_at(M, N, lam + (size_t)i * N * M, h + ((size_t)i * T + j) * N, m); \
+    } while (0)
+    ofc_mnmf_h(F, T, N, K, tp, va, h);
+    for (int i = 0; i < F; ++i) {
+        const cplx *xi = x + (size_t)i * T * M;
+        cplx *Pi = P + (size_t)i * M * M;
+        if (what & 1) {
+            ofc_weighted_cov(T, M, N, xi, lam + (size_t)i * N * M, h + (size_t)i * T * N, Q);
+            for (int m = 0; m < M; ++m) {
+                int st = ofc_ip_column(M, Pi, Q + (size_t)m * M * M, m);
+                if (st != OFC_OK) {
+                    status = st;
+                    goto done;
+                }
+            }
+        }
+        ofc_decorrelated_power(T, M, Pi, xi, U + (size_t)i * M * T);
+    }
+    if (what & 2) { /* Lambda: phi = h_{ijn}, sums over j */
+        SIG2();
+        for (int i = 0; i < F; ++i)
+            for (int n = 0; n < N; ++n)
+                for (int m = 0; m < M; ++m) {
+                    double a = 0.0, b = 0.0;
+                    for (int j = 0; j < T; ++j) {
+                        double s = s2[((size_t)i * T + j) * M + m];
+                        double hh = h[((size_t)i * T + j) * N + n];
+                        a += hh * U[((size_t)i * M + m) * T + j] / (s * s);
+                        b += hh / s;
+                    }
+                    lam[((size_t)i * N + n) * M + m] *= sqrt(a / b);
+                }
+    }
+    if (what & 4) { /* T: phi = lam_{imn} v_{jkn}, sums over j and m */
+        SIG2();
+        for (int i = 0; i < F; ++i)
+            for (int k = 0; k < K; ++k)
+                for (int n = 0; n < N; ++n) {
+                    double a = 0.0, b = 0.0;
+                    for (int j = 0; j < T; ++j)
+                        for (int m = 0; m < M; ++m) {
+                            double s = s2[((size_t)i * T + j) * M + m];
+                            double phi = lam[((size_t)i * N + n) * M + m] * va[((size_t)j * K + k) * N + n];
+                            a += phi * U[((size_t)i * M + m) * T + j] / (s * s);
+                            b += phi / s;
+                        }
+                    tp[((size_t)i * K + k) * N + n] *= sqrt(a / b);
+                }
+    }
+    if (what & 8) { /* V: phi = lam_{imn} t_{ikn}, sums over i and m */
+        SIG2();
+        for (size_t q = 0; q < (size_t)T * K * N; ++q)
+            num[q] = den[q] = 0.0;
+        for (int i = 0; i < F; ++i)
+            for (int j = 0; j < T; ++j)
+                for (int m = 0; m < M; ++m) {
+                    double s = s2[((size_t)i * T + j) * M + m];
+                    double u = U[((size_t)i * M + m) * T + j];
+                    for (int k = 0; k < K; ++k)
+                        for (int n = 0; n < N; ++n) {
+                            double phi = lam[((size_t)i * N + n) * M + m] * tp[((size_t)i * K + k) * N + n];
+                            num[((size_t)j * K + k) * N + n] += phi * u / (s * s);
+                            den[((size_t)j * K + k) * N + n] += phi / s;
+                        }
+                }
+        for (size_t q = 0; q < (size_t)T * K * N; ++q)
+            va[q] *= sqrt(num[q] / den[q]);
+    }
+#undef SIG2
+done:
+    free(h);
+    free(U);
+    free(s2);
+    free(Q);
+    free(num);
+    free(den);
+    return status;
+}
+
+/* n_iter FastMNMF iterations; ll_trace [n_iter] (LL per bin after each) or NULL. */
+int ofc_mnmf_fit(int F, int T, int M, int N, int K, const cplx *x, cplx *P, double *lam,
+                 double *tp, double *va, int n_iter, double *ll_trace)
+{
+    if (F < 1 || T < 1 || M < 1 || M > 64 || N < 1 || K < 1 || n_iter < 0)
+        return OFC_E_ARG;
+    for (int it = 0; it < n_iter; ++it) {
+        int st = ofc_mnmf_iterate(F, T, M, N, K, x, P, lam, tp, va, 15);
+        if (st != OFC_OK)
+            return st;
+        if (ll_trace)
+            ll_trace[it] = ofc_mnmf_loglik(F, T, M, N, K, x, P, lam, tp, va, NULL);
+    }
+    return OFC_OK;
+}
+
 int ofc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -91,6 +91,22 @@ def init_params_blocks(x, N, B, config_id=0, mixture_id=0):
     return P, lam, v
 
 
+def init_params_mnmf(x, N, K, config_id=0, mixture_id=0):
+    """Initial FastMNMF state: P = I, lam [F,N,M] = 0.5 + u, spectral patterns
+    tp [F,K,N] = a_f (0.5 + u'), activations va [T,K,N] = b_t (0.5 + u''),
+    with a_f b_t the rank-one fit of the mixture power |x_ft|^2 / (M N K)."""
+    F, T, M = x.shape
+    rng = _rng(config_id, mixture_id, 5)
+    p = (np.abs(x.astype(np.complex128)) ** 2).sum(axis=2)              # [F,T]
+    a = p.mean(axis=1) / (M * N * K) + 1e-12
+    b = p.mean(axis=0) / p.mean() + 1e-6
+    lam = (0.5 + rng.random((F, N, M))).astype(np.float32)
+    tp = (a[:, None, None] * (0.5 + rng.random((F, K, N)))).astype(np.float32)
+    va = (b[:, None, None] * (0.5 + rng.random((T, K, N)))).astype(np.float32)
+    P = np.broadcast_to(np.eye(M, dtype=np.complex128), (F, M, M)).copy()
+    return P, lam, tp, va
+
+
 def batch_specs(B=256, F=513, config_id=2, seed=0):
     """Shapes of the mixed batch: T ~ U{200..2000}, M in {2,3,4}, N in {M+1, M+2}."""
     rng = _rng(config_id, 10**6 + seed, 2)
