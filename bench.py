@@ -83,10 +83,11 @@ def main():
     ap.add_argument("--calib-copy", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--bpt", type=int, default=0)
-    ap.add_argument("--workload", choices=["headline", "batch", "large"], default="headline",
+    ap.add_argument("--workload", choices=["headline", "batch", "large", "blocks", "mnmf"], default="headline",
                     help="headline: the contract line (M=2 N=3 F=513 T=1000); batch: 256 mixed "
                          "mixtures in one persistent launch vs sequential runs; large: M=8 N=10 "
-                         "F=1025 T=4000")
+                         "F=1025 T=4000; blocks: the piecewise stationary model on the headline "
+                         "mixture (B=4); mnmf: FastMNMF on the headline mixture (K=8)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build measures the single-GPU kernel "
@@ -98,6 +99,10 @@ def main():
         return bench_batch(args)
     if args.workload == "large":
         return bench_large(args)
+    if args.workload == "blocks":
+        return bench_blocks(args)
+    if args.workload == "mnmf":
+        return bench_mnmf(args)
 
     import torch
 
@@ -308,6 +313,89 @@ def bench_large(args):
                         "frac": flops / (t * 1e-3) / FP32_FMA_PEAK, "traffic": None,
                         "hbm_GBps_algorithmic": (16 * M * iters + 8 * N) * F * T / (t * 1e-3) / 1e9}}
     print(json.dumps(out))
+
+
+def _headline_mixture():
+    from paper_2101_08563_amd import synth
+    cfg = synth.CONFIGS["c1"]
+    x = synth.mixture(F=cfg["F"], T=cfg["T"], M=cfg["M"], N=cfg["N"], rank=cfg["rank"], diffuse=cfg["diffuse"],
+                      config_id=cfg["config_id"])
+    return x, cfg
+
+
+def bench_blocks(args, B=4):
+    """Piecewise stationary model (Sec. VI) on the headline mixture, blocks of B frames."""
+    import torch
+
+    from paper_2101_08563_amd import FastFCA, synth
+
+    x, cfg = _headline_mixture()
+    F, T, M, N = x.shape[0], x.shape[1], x.shape[2], cfg["N"]
+    P0, lam0, v0 = synth.init_params_blocks(x, N, B, config_id=cfg["config_id"])
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        xd, Pd, ld, vd = (torch.from_numpy(a).cuda() for a in (x, P0, lam0, v0))
+    stream.synchronize()
+    ctx = FastFCA.from_blocks(xd, N, B, Pd, ld, vd, stream=stream)
+    iters = args.iters
+
+    def run():
+        ctx.set_params(Pd, ld, vd)
+        ctx.em_step(iters)
+
+    run()
+    ctx.sync()
+    t = _time(run, stream, max(3, args.steps // 4))
+    ctx.sync()
+    ctx.close()
+    J = T // B
+    updates = F * J * N * iters
+    print(json.dumps({"metric": "EM TF-bin*source updates/s", "value": updates / (t * 1e-3), "unit": "updates/s",
+                      "n_gpus": 1, "steps": max(3, args.steps // 4), "warmup": 1, "ms_per_step": t,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                      "data": "synthetic",
+                      "config": {"workload": "piecewise stationary model, blocks of %d frames: M=%d N=%d F=%d "
+                                             "T=%d (J=%d blocks), %d IP+EM iterations" % (B, M, N, F, T, J, iters),
+                                 "frames_per_s": F * T * iters / (t * 1e-3)}}))
+
+
+def bench_mnmf(args, K=8):
+    """FastMNMF (NMF source powers shared over frequencies) on the headline mixture."""
+    import torch
+
+    from paper_2101_08563_amd import FastFCA, synth
+
+    x, cfg = _headline_mixture()
+    F, T, M, N = x.shape[0], x.shape[1], x.shape[2], cfg["N"]
+    iters = min(args.iters, 30)
+    P0, lam0, t0, v0 = synth.init_params_mnmf(x, N, K, config_id=cfg["config_id"])
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        xd, Pd, ld, td, vd = (torch.from_numpy(a).cuda() for a in (x, P0, lam0, t0, v0))
+    stream.synchronize()
+    ctx = FastFCA.mnmf(xd, N, K, ld, td, vd, P0=Pd, stream=stream)
+
+    def run():
+        ctx.mnmf_set_params(Pd, ld, td, vd)
+        ctx.em_step(iters)
+
+    run()
+    ctx.sync()
+    reps = max(3, args.steps // 4)
+    t = _time(run, stream, reps)
+    ctx.sync()
+    ll = ctx.loglik()
+    ctx.close()
+    updates = F * T * N * iters
+    hbm = (8 * M + 16 * N) * F * T * iters   # x read; G, E written and read back, per iteration
+    print(json.dumps({"metric": "EM TF-bin*source updates/s", "value": updates / (t * 1e-3), "unit": "updates/s",
+                      "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": t, "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "FastMNMF: M=%d N=%d K=%d F=%d T=%d, %d IP+MM iterations"
+                                             % (M, N, K, F, T, iters), "ll_per_bin": ll,
+                                 "us_per_iteration": t * 1e3 / iters},
+                      "roofline": {"bound": "hbm", "achieved": hbm / (t * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
+                                   "unit": "GB/s", "frac": hbm / (t * 1e-3) / HBM_PEAK, "traffic": None}}))
 
 
 if __name__ == "__main__":

@@ -129,6 +129,37 @@ int fastfca_init_blocks(fastfca_ctx **out, const fastfca_c64 *x, int F, int T, i
 int fastfca_block_length(const fastfca_ctx *c, int b);
 
 /*
+ * fastfca_mnmf_init -- a context fitting FastMNMF (Sec. V, "FastMNMF:
+ * Full-band Extension of FastFCA", and its appendix): the source powers are
+ * an NMF over frequency and time, h_{ijn} = sum_k t_{ikn} v_{jkn}
+ * (eq:NMFconst2), and eq:FastMNMFcost is minimized by IP for every P(f)
+ * (eq:ip1, eq:ip2) and by the multiplicative MM rule for Lambda, then T, then
+ * V, each rule theta <- theta sqrt(sum phi U / sigma^4 / sum phi / sigma^2)
+ * for the coefficient phi of theta in sigma^2.
+ *   x       device [F][T][M] complex64 (copied)
+ *   K       NMF bases per source, 1..32
+ *   P0      device [F][M][M] complex128, or NULL for P = I
+ *   lambda0 device [F][N][M] > 0 (required)
+ *   t0      device [F][K][N] > 0, spectral patterns t_{ikn} (required)
+ *   v0      device [T][K][N] > 0, activations v_{jkn} (required)
+ * M <= 4, N <= 6, T <= 2048 (E_UNSUPPORTED otherwise). fastfca_em_step runs
+ * IP+MM iterations (one per-frequency launch and one pass over frames per
+ * iteration); fastfca_loglik, fastfca_ll_trace and fastfca_mwf use the
+ * current h, which fastfca_get_params returns as v [F][T][N]. set_config,
+ * autotune and set_algorithm return E_STATE / E_UNSUPPORTED. An activation
+ * that reaches zero or a non-finite value is reported as E_NONFINITE.
+ */
+int fastfca_mnmf_init(fastfca_ctx **out, const fastfca_c64 *x, int F, int T, int M, int N, int K,
+                      const fastfca_c128 *P0, const float *lambda0, const float *t0,
+                      const float *v0, void *hip_stream);
+
+/* FastMNMF factors (device pointers, any may be NULL): P [F][M][M],
+ * lambda [F][N][M], t [F][K][N], v [T][K][N]. E_STATE for other contexts. */
+int fastfca_mnmf_get_params(fastfca_ctx *c, fastfca_c128 *P, float *lambda, float *t, float *v);
+int fastfca_mnmf_set_params(fastfca_ctx *c, const fastfca_c128 *P, const float *lambda,
+                            const float *t, const float *v);
+
+/*
  * fastfca_em_step -- run n_iter >= 1 iterations of Algorithm 1 (IP sweep over
  * m = 1..M using eq:wsampcov, eq:ip1, eq:ip2; U by eq:Udef; EM update of
  * L[:,n] then H[n,:] for n = 1..N in order) on every frequency of every

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfastfca.so")
 # (source, extra defines, object name); the wide family is compiled once per M
-SOURCES = [("em_kernel.hip", [], "em_kernel.o"), ("em_cov_kernel.hip", [], "em_cov_kernel.o"), ("aux_kernels.hip", [], "aux_kernels.o"),
+SOURCES = [("em_kernel.hip", [], "em_kernel.o"), ("em_cov_kernel.hip", [], "em_cov_kernel.o"),
+           ("mnmf_kernels.hip", [], "mnmf_kernels.o"), ("aux_kernels.hip", [], "aux_kernels.o"),
            ("runtime.hip", [], "runtime.o"), ("synth_kernels.hip", [], "synth_kernels.o"),
            ("net_kernels.hip", [], "net_kernels.o"), ("net_api.hip", [], "net_api.o")] + [
     ("em_wide_kernel.hip", ["-DFFCA_WIDE_M=%d" % m], "em_wide_m%d.o" % m) for m in range(2, 9)]

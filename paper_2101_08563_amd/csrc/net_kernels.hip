@@ -339,7 +339,6 @@ __global__ void pit_loss_kernel(const float *lv, const float *tv, const float *l
             __syncthreads();
         }
     __shared__ int best_perm[kPitMaxN];
-    __shared__ float best_loss;
     if (tid == 0) {
         int p[kPitMaxN];
         for (int n = 0; n < N; ++n) p[n] = n;
@@ -374,7 +373,6 @@ __global__ void pit_loss_kernel(const float *lv, const float *tv, const float *l
                 p[b] = tmp;
             }
         }
-        best_loss = best;
         for (int n = 0; n < N; ++n) best_perm[n] = bp[n];
         loss[s] = best;
         if (perm_out)

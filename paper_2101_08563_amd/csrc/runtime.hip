@@ -15,6 +15,7 @@
 
 #include "../../include/fastfca.h"
 #include "internal.hpp"
+#include "mnmf.hpp"
 
 namespace ffca {
 hipError_t launch_pinv(const WorkItem *items, int n_items, int M, float2 *Bh, double *ldet,
@@ -57,6 +58,16 @@ struct ClassCfg {
     std::vector<int> items;  // item indices of this class, in launch order
 };
 
+// FastMNMF state (fastfca_mnmf_init): NMF factors and the V-rule scratch.
+struct MnmfState {
+    int K = 0, threads = 0, bpt = 0;
+    float *tp = nullptr;    // [F][K][N]
+    float *va = nullptr;    // [T][K][N]
+    float *G = nullptr, *E = nullptr;  // [F][T][N]
+    float *part = nullptr;  // [chunks][2][K][T][N]
+    int *vflag = nullptr;
+};
+
 }  // namespace
 
 struct fastfca_ctx {
@@ -79,6 +90,7 @@ struct fastfca_ctx {
     hipGraphExec_t graph_exec = nullptr;
     int graph_n_iter = -1;
     int algo = kAlgoEM;
+    MnmfState *mn = nullptr;          // FastMNMF context
     std::string err;
     char arch[64] = {0};
 };
@@ -444,7 +456,39 @@ int create(fastfca_ctx **out, int B, const fastfca_problem *probs, uint64_t seed
     return FASTFCA_OK;
 }
 
+int record_mnmf(fastfca_ctx *c, int n_iter) {
+    auto &p = c->probs[0];
+    auto &mn = *c->mn;
+    MnmfLaunch a{};
+    a.x = p.x;
+    a.P = p.P;
+    a.lam = p.lam;
+    a.tp = mn.tp;
+    a.va = mn.va;
+    a.G = mn.G;
+    a.E = mn.E;
+    a.ll_trace = c->d_trace;
+    a.cap = c->trace_cap;
+    a.ldet = p.ldet;
+    a.status = c->d_status;
+    a.F = p.F;
+    a.T = p.T;
+    a.K = mn.K;
+    for (int it = 0; it <= n_iter; ++it) {
+        a.iter = it;
+        a.ll_only = it == n_iter;
+        HIPCHK(c, launch_mnmf_freq(p.M, p.N, mn.bpt, mn.threads, a, c->stream));
+        if (it < n_iter)
+            HIPCHK(c, launch_mnmf_v(mn.G, mn.E, mn.tp, mn.part, mn.va, p.F, p.T, p.N, mn.K, kMnmfFChunk, mn.vflag,
+                                    c->stream));
+    }
+    // the frame-model h for the likelihood, MWF and parameter calls
+    HIPCHK(c, launch_mnmf_h(mn.tp, mn.va, p.v, p.F, p.T, p.N, mn.K, c->stream));
+    return FASTFCA_OK;
+}
+
 int record_em(fastfca_ctx *c, int n_iter) {
+    if (c->mn) return record_mnmf(c, n_iter);
     if (c->persistent) {
         HIPCHK(c, launch_fill_int(c->d_queue, 1, 0, c->stream));
         EmLaunch a{c->d_items, static_cast<int>(c->h_items.size()), n_iter, c->d_queue, c->algo};
@@ -468,9 +512,13 @@ int record_em(fastfca_ctx *c, int n_iter) {
 int check_status(fastfca_ctx *c) {
     const int total = static_cast<int>(c->h_items.size());
     std::vector<int> st(total);
+    int vflag = 0;
     HIPCHK(c, hipMemcpyAsync(st.data(), c->d_status, sizeof(int) * total, hipMemcpyDeviceToHost,
                              c->stream));
+    if (c->mn)
+        HIPCHK(c, hipMemcpyAsync(&vflag, c->mn->vflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (vflag) return set_err(c, FASTFCA_E_NONFINITE, "FastMNMF: an activation v became zero or non-finite");
     for (size_t b = 0; b < c->probs.size(); ++b) {
         const auto &p = c->probs[b];
         for (int f = 0; f < p.F; ++f) {
@@ -509,6 +557,84 @@ int fastfca_init_blocks(fastfca_ctx **out, const fastfca_c64 *x, int F, int T, i
     if (block_len < 1) return set_err(nullptr, FASTFCA_E_ARG, "block length must be >= 1");
     fastfca_problem d{x, F, T, M, N, P0, lambda0, v0};
     return create(out, 1, &d, seed, hip_stream, block_len);
+}
+
+int fastfca_mnmf_init(fastfca_ctx **out, const fastfca_c64 *x, int F, int T, int M, int N, int K,
+                      const fastfca_c128 *P0, const float *lambda0, const float *t0, const float *v0,
+                      void *hip_stream) {
+    if (!out) return set_err(nullptr, FASTFCA_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!lambda0 || !t0 || !v0) return set_err(nullptr, FASTFCA_E_ARG, "FastMNMF needs lambda0, t0 and v0");
+    if (K < 1 || K > kMnmfKMax) return set_err(nullptr, FASTFCA_E_ARG, "K=%d outside 1..%d", K, kMnmfKMax);
+    if (M < 2 || M > 4 || N < 2 || N > kMnmfNMax || T > kResidentBins)
+        return set_err(nullptr, FASTFCA_E_UNSUPPORTED, "FastMNMF runs M<=4, N<=%d, T<=%d (M=%d N=%d T=%d)",
+                       kMnmfNMax, kResidentBins, M, N, T);
+    fastfca_problem d{x, F, T, M, N, P0, lambda0, nullptr};
+    // frame-model context for x, P, Lambda, h (= v) and the likelihood/MWF kernels
+    int rc = create(out, 1, &d, 0, hip_stream);
+    if (rc != FASTFCA_OK) return rc;
+    fastfca_ctx *c = *out;
+    auto *mn = new MnmfState();
+    c->mn = mn;
+    mn->K = K;
+    mn->bpt = N >= 6 ? 8 : 4;
+    mn->threads = threads_for(T, mn->bpt);
+    const size_t Fs = F, Ts = T, Ns = N, Ks = K;
+    const size_t nchunk = (F + kMnmfFChunk - 1) / kMnmfFChunk;
+    int *flag = nullptr;
+    int hflag[2] = {0, 0};
+    hipError_t e = hipSuccess;
+    if ((rc = dalloc(c, &mn->tp, Fs * Ks * Ns)) == FASTFCA_OK && (rc = dalloc(c, &mn->va, Ts * Ks * Ns)) == FASTFCA_OK &&
+        (rc = dalloc(c, &mn->G, Fs * Ts * Ns)) == FASTFCA_OK && (rc = dalloc(c, &mn->E, Fs * Ts * Ns)) == FASTFCA_OK &&
+        (rc = dalloc(c, &mn->part, nchunk * 2 * Ks * Ts * Ns)) == FASTFCA_OK &&
+        (rc = dalloc(c, &mn->vflag, 1)) == FASTFCA_OK && (rc = dalloc(c, &flag, 2)) == FASTFCA_OK) {
+        e = hipMemcpyAsync(mn->tp, t0, sizeof(float) * Fs * Ks * Ns, hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(mn->va, v0, sizeof(float) * Ts * Ks * Ns, hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = launch_fill_int(mn->vflag, 1, 0, c->stream);
+        if (e == hipSuccess) e = launch_fill_int(flag, 2, 0, c->stream);
+        if (e == hipSuccess) e = launch_check_positive(mn->tp, Fs * Ks * Ns, flag, c->stream);
+        if (e == hipSuccess) e = launch_check_positive(mn->va, Ts * Ks * Ns, flag + 1, c->stream);
+        if (e == hipSuccess) e = launch_mnmf_h(mn->tp, mn->va, c->probs[0].v, F, T, N, K, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) rc = set_err(c, FASTFCA_E_HIP, "FastMNMF init: %s", hipGetErrorString(e));
+        else if (hflag[0] || hflag[1]) rc = set_err(c, FASTFCA_E_ARG, "t0 and v0 must be finite and > 0");
+    }
+    hipFree(flag);
+    if (rc != FASTFCA_OK) {
+        g_init_error = c->err;
+        fastfca_destroy(c);
+        *out = nullptr;
+    }
+    return rc;
+}
+
+int fastfca_mnmf_get_params(fastfca_ctx *c, fastfca_c128 *P, float *lambda, float *t, float *v) {
+    if (!c || !c->mn) return c ? set_err(c, FASTFCA_E_STATE, "not a FastMNMF context") : FASTFCA_E_ARG;
+    auto &p = c->probs[0];
+    const size_t F = p.F, T = p.T, M = p.M, N = p.N, K = c->mn->K;
+    if (P) HIPCHK(c, hipMemcpyAsync(P, p.P, sizeof(double2) * F * M * M, hipMemcpyDeviceToDevice, c->stream));
+    if (lambda)
+        HIPCHK(c, hipMemcpyAsync(lambda, p.lam, sizeof(float) * F * N * M, hipMemcpyDeviceToDevice, c->stream));
+    if (t) HIPCHK(c, hipMemcpyAsync(t, c->mn->tp, sizeof(float) * F * K * N, hipMemcpyDeviceToDevice, c->stream));
+    if (v) HIPCHK(c, hipMemcpyAsync(v, c->mn->va, sizeof(float) * T * K * N, hipMemcpyDeviceToDevice, c->stream));
+    return FASTFCA_OK;
+}
+
+int fastfca_mnmf_set_params(fastfca_ctx *c, const fastfca_c128 *P, const float *lambda, const float *t,
+                            const float *v) {
+    if (!c || !c->mn) return c ? set_err(c, FASTFCA_E_STATE, "not a FastMNMF context") : FASTFCA_E_ARG;
+    auto &p = c->probs[0];
+    const size_t F = p.F, T = p.T, M = p.M, N = p.N, K = c->mn->K;
+    if (P) HIPCHK(c, hipMemcpyAsync(p.P, P, sizeof(double2) * F * M * M, hipMemcpyDeviceToDevice, c->stream));
+    if (lambda)
+        HIPCHK(c, hipMemcpyAsync(p.lam, lambda, sizeof(float) * F * N * M, hipMemcpyDeviceToDevice, c->stream));
+    if (t) HIPCHK(c, hipMemcpyAsync(c->mn->tp, t, sizeof(float) * F * K * N, hipMemcpyDeviceToDevice, c->stream));
+    if (v) HIPCHK(c, hipMemcpyAsync(c->mn->va, v, sizeof(float) * T * K * N, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, launch_mnmf_h(c->mn->tp, c->mn->va, p.v, p.F, p.T, p.N, c->mn->K, c->stream));
+    HIPCHK(c, launch_fill_int(c->d_status, p.F, ST_OK, c->stream));
+    HIPCHK(c, launch_fill_int(c->mn->vflag, 1, 0, c->stream));
+    return FASTFCA_OK;
 }
 
 int fastfca_block_length(const fastfca_ctx *c, int b) {
@@ -650,6 +776,7 @@ int fastfca_num_problems(const fastfca_ctx *c) { return c ? static_cast<int>(c->
 
 int fastfca_set_config(fastfca_ctx *c, int threads, int bins_per_thread) {
     if (!c) return FASTFCA_E_ARG;
+    if (c->mn) return set_err(c, FASTFCA_E_STATE, "FastMNMF contexts use a fixed launch shape");
     if (threads == 0 && bins_per_thread == 0) {
         for (auto &cc : c->classes) pick_class(cc);
         drop_graph(c);
@@ -692,6 +819,7 @@ int fastfca_set_algorithm(fastfca_ctx *c, int algo) {
     if (!c) return FASTFCA_E_ARG;
     if (algo != FASTFCA_ALGO_EM && algo != FASTFCA_ALGO_MM)
         return set_err(c, FASTFCA_E_ARG, "unknown algorithm %d", algo);
+    if (c->mn) return set_err(c, FASTFCA_E_UNSUPPORTED, "FastMNMF updates Lambda, T and V by MM only");
     if (algo == FASTFCA_ALGO_MM)
         for (const auto &cc : c->classes)
             if (cc.wide)
@@ -722,6 +850,7 @@ int fastfca_get_config(const fastfca_ctx *c, int b, int *threads, int *bins_per_
 
 int fastfca_autotune(fastfca_ctx *c, int n_iter, const char *cache_path) {
     if (!c || n_iter < 1) return c ? set_err(c, FASTFCA_E_ARG, "n_iter must be >= 1") : FASTFCA_E_ARG;
+    if (c->mn) return set_err(c, FASTFCA_E_STATE, "FastMNMF contexts use a fixed launch shape");
     int rc = fastfca_sync(c);
     if (rc != FASTFCA_OK) return rc;
     if (n_iter > c->trace_cap && (rc = upload_items(c, n_iter)) != FASTFCA_OK) return rc;
@@ -894,6 +1023,15 @@ void fastfca_destroy(fastfca_ctx *c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     drop_graph(c);
     for (auto &p : c->probs) free_problem(p);
+    if (c->mn) {
+        hipFree(c->mn->tp);
+        hipFree(c->mn->va);
+        hipFree(c->mn->G);
+        hipFree(c->mn->E);
+        hipFree(c->mn->part);
+        hipFree(c->mn->vflag);
+        delete c->mn;
+    }
     hipFree(c->d_items);
     hipFree(c->d_status);
     hipFree(c->d_trace);

@@ -41,6 +41,9 @@ SIGNATURES = {
     "fastfca_set_algorithm": (_i, [_vp, _i]),
     "fastfca_init_blocks": (_i, [ctypes.POINTER(_vp), _vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _u64, _vp]),
     "fastfca_block_length": (_i, [_vp, _i]),
+    "fastfca_mnmf_init": (_i, [ctypes.POINTER(_vp), _vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]),
+    "fastfca_mnmf_get_params": (_i, [_vp, _vp, _vp, _vp, _vp]),
+    "fastfca_mnmf_set_params": (_i, [_vp, _vp, _vp, _vp, _vp]),
     "fastfca_synth_mixture": (_i, [_vp, _i, _i, _i, _i, _i, ctypes.c_float, _u64, _vp]),
     "fastfca_last_error": (ctypes.c_char_p, [_vp]),
     "fastfca_destroy": (None, [_vp]),
@@ -167,6 +170,47 @@ class FastFCA:
         if rc != OK:
             raise FastFCAError(rc, lib.fastfca_last_error(None).decode())
         return cls(stream=stream, _ctx=ctx)
+
+    @classmethod
+    def mnmf(cls, x, N, K, lam0, t0, v0, P0=None, stream=None):
+        """FastMNMF (NMF source powers h = sum_k t_{ikn} v_{jkn}): lam0 [F,N,M],
+        t0 [F,K,N], v0 [T,K,N] float32, P0 [F,M,M] complex128 or None."""
+        lib = load_library()
+        stream = stream if stream is not None else torch.cuda.current_stream()
+        F, T, M = x.shape
+        _check_dev(x, torch.complex64, (F, T, M), "x")
+        _check_dev(P0, torch.complex128, (F, M, M), "P0")
+        _check_dev(lam0, torch.float32, (F, N, M), "lam0")
+        _check_dev(t0, torch.float32, (F, K, N), "t0")
+        _check_dev(v0, torch.float32, (T, K, N), "v0")
+        ctx = ctypes.c_void_p()
+        rc = lib.fastfca_mnmf_init(ctypes.byref(ctx), _ptr(x), F, T, M, int(N), int(K), _ptr(P0), _ptr(lam0),
+                                   _ptr(t0), _ptr(v0), _stream(stream))
+        if rc != OK:
+            raise FastFCAError(rc, lib.fastfca_last_error(None).decode())
+        obj = cls(stream=stream, _ctx=ctx)
+        obj._mnmf_K = int(K)
+        return obj
+
+    def mnmf_get_params(self):
+        """(P [F,M,M], lam [F,N,M], t [F,K,N], v [T,K,N]) of a FastMNMF context."""
+        F, T, M, N = self.shape()
+        K = self._mnmf_K
+        P = torch.empty((F, M, M), dtype=torch.complex128, device="cuda")
+        lam = torch.empty((F, N, M), dtype=torch.float32, device="cuda")
+        t = torch.empty((F, K, N), dtype=torch.float32, device="cuda")
+        v = torch.empty((T, K, N), dtype=torch.float32, device="cuda")
+        self._chk(self._lib.fastfca_mnmf_get_params(self._ctx, _ptr(P), _ptr(lam), _ptr(t), _ptr(v)))
+        return P, lam, t, v
+
+    def mnmf_set_params(self, P=None, lam=None, t=None, v=None):
+        F, T, M, N = self.shape()
+        K = self._mnmf_K
+        _check_dev(P, torch.complex128, (F, M, M), "P")
+        _check_dev(lam, torch.float32, (F, N, M), "lam")
+        _check_dev(t, torch.float32, (F, K, N), "t")
+        _check_dev(v, torch.float32, (T, K, N), "v")
+        self._chk(self._lib.fastfca_mnmf_set_params(self._ctx, _ptr(P), _ptr(lam), _ptr(t), _ptr(v)))
 
     @classmethod
     def from_batch(cls, problems, seed=0, stream=None):

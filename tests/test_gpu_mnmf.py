@@ -1,0 +1,77 @@
+"""GPU parity of FastMNMF (Sec. V and its appendix) against the FP64 oracle:
+IP for every W_i, multiplicative MM rules for Lambda, T and V with the
+activations shared across frequencies. Bars as for the frame model: normwise
+1e-4 on P, lambda, the NMF factors t and v, the powers h and every y_n; 1e-6
+nats per bin on the LL; the per-iteration trace within 1e-4."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2101_08563_amd import FastFCA, FastFCAError, synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+REL_TOL = 1e-4
+LL_TOL = 1e-6
+
+
+def rel(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+
+
+def dev(*arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in arrs]
+
+
+@pytest.mark.parametrize("M,N,K,F,T", [(2, 3, 4, 33, 400), (3, 4, 8, 17, 300), (4, 5, 2, 9, 250),
+                                       (2, 6, 16, 13, 500), (2, 2, 1, 70, 129)])
+def test_fastmnmf_parity(M, N, K, F, T):
+    iters = 15
+    x = synth.mixture(F=F, T=T, M=M, N=N, rank=8, diffuse=0.05, config_id=95, mixture_id=K)
+    P0, lam0, t0, v0 = synth.init_params_mnmf(x, N, K, config_id=95, mixture_id=K)
+    xd, Pd, ld, td, vd = dev(x, P0, lam0, t0, v0)
+    ctx = FastFCA.mnmf(xd, N, K, ld, td, vd, P0=Pd)
+    ctx.em_step(iters)
+    ctx.sync()
+    trace = ctx.ll_trace()
+    ll = ctx.loglik()
+    P, lam, t, v = (a.cpu().numpy() for a in ctx.mnmf_get_params())
+    h = ctx.get_params()[2].cpu().numpy()
+    y = ctx.mwf().cpu().numpy()
+    ctx.close()
+    Po, lo, to, vo, tro = oracle.mnmf_fit(x, P0, lam0, t0, v0, iters, trace=True)
+    ho = oracle.mnmf_h(to, vo)
+    llo, _ = oracle.mnmf_loglik(x, Po, lo, to, vo)
+    yo = oracle.mwf(x, Po, lo, ho)
+    errs = dict(P=rel(P, Po), lam=rel(lam, lo), t=rel(t, to), v=rel(v, vo), h=rel(h, ho), ll=abs(ll - llo),
+                y=max(rel(y[n], yo[n]) for n in range(N)), trace=float(np.abs(trace - tro).max()))
+    print("mnmf M%d N%d K%d F%d T%d" % (M, N, K, F, T), errs, flush=True)
+    for k in ("P", "lam", "t", "v", "h", "y"):
+        assert errs[k] < REL_TOL, errs
+    assert errs["ll"] < LL_TOL and errs["trace"] < 1e-4, errs
+    assert np.diff(trace).min() > -1e-5
+
+
+def test_fastmnmf_restart_and_errors():
+    x = synth.mixture(F=5, T=100, M=2, N=3, rank=4, config_id=96)
+    P0, lam0, t0, v0 = synth.init_params_mnmf(x, 3, 2, config_id=96)
+    xd, Pd, ld, td, vd = dev(x, P0, lam0, t0, v0)
+    ctx = FastFCA.mnmf(xd, 3, 2, ld, td, vd)
+    ctx.em_step(4)
+    a = [u.cpu().numpy() for u in ctx.mnmf_get_params()]
+    ctx.mnmf_set_params(Pd, ld, td, vd)   # back to the start: same trajectory, bitwise
+    ctx.em_step(4)
+    b = [u.cpu().numpy() for u in ctx.mnmf_get_params()]
+    for u, w in zip(a, b):
+        assert np.array_equal(u, w)
+    with pytest.raises(FastFCAError) as e:
+        ctx.set_config(256, 4)
+    assert e.value.code == -6
+    ctx.close()
+    x5 = synth.mixture(F=2, T=50, M=5, N=6, config_id=97)
+    P5, l5, t5, v5 = synth.init_params_mnmf(x5, 6, 2, config_id=97)
+    with pytest.raises(FastFCAError) as e:
+        FastFCA.mnmf(*dev(x5), 6, 2, *dev(l5, t5, v5))
+    assert e.value.code == -7
