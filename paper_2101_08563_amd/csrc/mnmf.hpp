@@ -15,7 +15,7 @@ struct MnmfLaunch {
     double2 *P;        // [F][M][M]
     float *lam;        // [F][N][M]
     float *tp;         // [F][K][N] spectral patterns t_{ikn}
-    const float *va;   // [T][K][N] activations v_{jkn}
+    const float *va;   // [K][N][T] activations v_{jkn} (frames contiguous)
     float *G, *E;      // [F][T][N] V-rule terms
     double *ll_trace;  // [F][cap]
     int cap;
@@ -30,6 +30,8 @@ bool mnmf_supported(int M, int N, int bpt);
 hipError_t launch_mnmf_freq(int M, int N, int bpt, int threads, const MnmfLaunch &a, hipStream_t s);
 hipError_t launch_mnmf_v(const float *G, const float *E, const float *tp, float *part, float *va, int F, int T,
                          int N, int K, int fchunk, int *flag, hipStream_t s);
+// out[c][r] = in[r][c]: activations between the ABI layout [T][K][N] and [K][N][T]
+hipError_t launch_transpose(const float *in, float *out, int R, int C, hipStream_t s);
 hipError_t launch_mnmf_h(const float *tp, const float *va, float *h, int F, int T, int N, int K, hipStream_t s);
 
 }  // namespace ffca

@@ -111,10 +111,12 @@ __global__ void __launch_bounds__(kResidentBins / BPT) mnmf_freq_kernel(MnmfLaun
 #pragma unroll
             for (int n = 0; n < N; ++n) s[n] = 0.0f;
             if (t < T) {
-                const float *vt = a.va + static_cast<size_t>(t) * K * N;
+                const float *vt = a.va + t;  // activations stored [K][N][T]
+#pragma unroll 8
                 for (int kk = 0; kk < K; ++kk)
 #pragma unroll
-                    for (int n = 0; n < N; ++n) s[n] = fmaf(sm.t[kk * N + n], vt[kk * N + n], s[n]);
+                    for (int n = 0; n < N; ++n)
+                        s[n] = fmaf(sm.t[kk * N + n], vt[static_cast<size_t>(kk * N + n) * T], s[n]);
             }
 #pragma unroll
             for (int n = 0; n < N; ++n) h[k][n] = t < T ? s[n] : 1.0f;
@@ -302,13 +304,13 @@ __global__ void __launch_bounds__(kResidentBins / BPT) mnmf_freq_kernel(MnmfLaun
             for (int k = 0; k < BPT; ++k) {
                 const int t = tid + k * nthr;
                 if (t < T) {
-                    const float *vt = a.va + static_cast<size_t>(t) * K * N;
+                    const float *vt = a.va + t;
 #pragma unroll
                     for (int c = 0; c < KC; ++c) {
                         if (k0 + c < K) {
 #pragma unroll
                             for (int n = 0; n < N; ++n) {
-                                const float vv = vt[(k0 + c) * N + n];
+                                const float vv = vt[static_cast<size_t>((k0 + c) * N + n) * T];
                                 nd[c * N + n] = fmaf(vv, an[k][n], nd[c * N + n]);
                                 nd[KC * N + c * N + n] = fmaf(vv, bn[k][n], nd[KC * N + c * N + n]);
                             }
@@ -385,65 +387,74 @@ __global__ void __launch_bounds__(kResidentBins / BPT) mnmf_freq_kernel(MnmfLaun
 // ------------------------------------------------------------------ V rule
 // Partial sums over the frequencies of chunk blockIdx.y for (j, n) =
 // divmod(index, N): part[chunk][0][k][index] = sum_i t_ikn G_ijn and
-// part[chunk][1][k][index] = sum_i t_ikn E_ijn.
-__global__ void __launch_bounds__(256) mnmf_v_partial_kernel(const float *G, const float *E, const float *tp,
-                                                             float *part, int F, int T, int N, int K,
-                                                             int fchunk) {
+// part[chunk][1][k][index] = sum_i t_ikn E_ijn. The chunk's t is staged in
+// LDS; G and E loads are coalesced over the index.
+__global__ void __launch_bounds__(64) mnmf_v_partial_kernel(const float *G, const float *E, const float *tp,
+                                                            float *part, int F, int T, int N, int K,
+                                                            int fchunk) {
+    __shared__ float ts[kMnmfFChunk * kMnmfKMax * kMnmfNMax];
+    const int c = blockIdx.y;
+    const int i0 = c * fchunk;
+    const int ni = min(F, i0 + fchunk) - i0;
+    // t of the chunk, [ii][k][n]; zero past the last frequency
+    for (int q = threadIdx.x; q < kMnmfFChunk * K * N; q += blockDim.x)
+        ts[q] = q < ni * K * N ? tp[static_cast<size_t>(i0) * K * N + q] : 0.0f;
+    __syncthreads();
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const int TN = T * N;
     if (idx >= TN) return;
     const int n = idx % N;
-    const int c = blockIdx.y;
-    const int i0 = c * fchunk;
-    const int i1 = min(F, i0 + fchunk);
-    float num[kMnmfKMax], den[kMnmfKMax];
+    const float *Gp = G + static_cast<size_t>(i0) * TN + idx;
+    const float *Ep = E + static_cast<size_t>(i0) * TN + idx;
+    // every load of the chunk in flight before the first FMA
+    float gs[kMnmfFChunk], es[kMnmfFChunk];
 #pragma unroll
-    for (int k = 0; k < kMnmfKMax; ++k) num[k] = den[k] = 0.0f;
-    for (int i = i0; i < i1; ++i) {
-        const float g = G[static_cast<size_t>(i) * TN + idx];
-        const float e = E[static_cast<size_t>(i) * TN + idx];
-        const float *ti = tp + static_cast<size_t>(i) * K * N + n;
-#pragma unroll
-        for (int k = 0; k < kMnmfKMax; ++k) {
-            if (k < K) {
-                const float tk = ti[k * N];
-                num[k] = fmaf(tk, g, num[k]);
-                den[k] = fmaf(tk, e, den[k]);
-            }
-        }
+    for (int ii = 0; ii < kMnmfFChunk; ++ii) {
+        gs[ii] = ii < ni ? Gp[static_cast<size_t>(ii) * TN] : 0.0f;
+        es[ii] = ii < ni ? Ep[static_cast<size_t>(ii) * TN] : 0.0f;
     }
-    float *pn = part + static_cast<size_t>(c) * 2 * K * TN;
-#pragma unroll
-    for (int k = 0; k < kMnmfKMax; ++k) {
-        if (k < K) {
-            pn[static_cast<size_t>(k) * TN + idx] = num[k];
-            pn[static_cast<size_t>(K + k) * TN + idx] = den[k];
-        }
-    }
-}
-
-// v_jkn <- v_jkn sqrt(num / den), the chunk partials summed in chunk order.
-__global__ void __launch_bounds__(256) mnmf_v_update_kernel(const float *part, float *va, int nchunk, int T,
-                                                            int N, int K, int *flag) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int TN = T * N;
-    if (idx >= TN) return;
-    const int j = idx / N, n = idx % N;
+    float *pn = part + static_cast<size_t>(c) * 2 * K * TN + idx;
     for (int k = 0; k < K; ++k) {
         float num = 0.0f, den = 0.0f;
-        for (int c = 0; c < nchunk; ++c) {
-            const float *pc = part + static_cast<size_t>(c) * 2 * K * TN;
-            num += pc[static_cast<size_t>(k) * TN + idx];
-            den += pc[static_cast<size_t>(K + k) * TN + idx];
+        const float *tk = ts + k * N + n;
+#pragma unroll
+        for (int ii = 0; ii < kMnmfFChunk; ++ii) {
+            const float t = tk[ii * K * N];
+            num = fmaf(t, gs[ii], num);
+            den = fmaf(t, es[ii], den);
         }
-        float *v = va + (static_cast<size_t>(j) * K + k) * N + n;
-        const float nv = *v * sqrtf(num / den);
-        if (!(nv > 0.0f) || !(nv < INFINITY)) *flag = 1;
-        *v = nv;
+        pn[static_cast<size_t>(k) * TN] = num;
+        pn[static_cast<size_t>(K + k) * TN] = den;
     }
 }
 
-// h_fjn = sum_k t_fkn v_jkn into the frame-model layout [F][T][N], so that
+// v_jkn <- v_jkn sqrt(num / den), the chunk partials summed in chunk order;
+// one thread per (k, n, j), activations stored [K][N][T].
+__global__ void __launch_bounds__(256) mnmf_v_update_kernel(const float *part, float *va, int nchunk, int T,
+                                                            int N, int K, int *flag) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int TN = T * N;
+    if (gid >= TN * K) return;
+    const int k = gid / TN;
+    const int rem = gid - k * TN;
+    const int n = rem / T, j = rem - n * T;
+    const int idx = j * N + n;
+    float num = 0.0f, den = 0.0f;
+    const float *pc = part + static_cast<size_t>(k) * TN + idx;
+    const size_t cs = static_cast<size_t>(2) * K * TN;
+    const size_t ds = static_cast<size_t>(K) * TN;
+#pragma unroll 8
+    for (int c = 0; c < nchunk; ++c) {
+        num += pc[c * cs];
+        den += pc[c * cs + ds];
+    }
+    float *v = va + static_cast<size_t>(gid);  // (k N + n) T + j
+    const float nv = *v * sqrtf(num / den);
+    if (!(nv > 0.0f) || !(nv < INFINITY)) *flag = 1;
+    *v = nv;
+}
+
+// h_fjn = sum_k t_fkn v_jkn (v stored [K][N][T]) into the frame-model layout [F][T][N], so that
 // the likelihood, MWF and parameter calls of the frame model apply.
 __global__ void mnmf_h_kernel(const float *tp, const float *va, float *h, int F, int T, int N, int K) {
     const size_t idx = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -455,8 +466,16 @@ __global__ void mnmf_h_kernel(const float *tp, const float *va, float *h, int F,
     const int f = static_cast<int>(ft / T);
     float s = 0.0f;
     for (int k = 0; k < K; ++k)
-        s = fmaf(tp[(static_cast<size_t>(f) * K + k) * N + n], va[(static_cast<size_t>(j) * K + k) * N + n], s);
+        s = fmaf(tp[(static_cast<size_t>(f) * K + k) * N + n], va[static_cast<size_t>(k * N + n) * T + j], s);
     h[idx] = s;
+}
+
+// out[c][r] = in[r][c] for an R x C matrix (activation layout changes).
+__global__ void transpose_kernel(const float *in, float *out, int R, int C) {
+    const size_t idx = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= static_cast<size_t>(R) * C) return;
+    const int r = static_cast<int>(idx / C), c = static_cast<int>(idx % C);
+    out[static_cast<size_t>(c) * R + r] = in[idx];
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -506,12 +525,20 @@ hipError_t launch_mnmf_v(const float *G, const float *E, const float *tp, float 
     if (K < 1 || K > kMnmfKMax || fchunk < 1) return hipErrorInvalidValue;
     const int nchunk = (F + fchunk - 1) / fchunk;
     const int TN = T * N;
-    hipLaunchKernelGGL(mnmf_v_partial_kernel, dim3((TN + 255) / 256, nchunk), dim3(256), 0, s, G, E, tp, part,
-                       F, T, N, K, fchunk);
+    if (fchunk > kMnmfFChunk || N > kMnmfNMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(mnmf_v_partial_kernel, dim3((TN + 63) / 64, nchunk), dim3(64), 0, s, G, E, tp, part, F, T,
+                       N, K, fchunk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(mnmf_v_update_kernel, dim3((TN + 255) / 256), dim3(256), 0, s, part, va, nchunk, T, N, K,
-                       flag);
+    hipLaunchKernelGGL(mnmf_v_update_kernel, dim3((TN * K + 255) / 256), dim3(256), 0, s, part, va, nchunk, T, N,
+                       K, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(const float *in, float *out, int R, int C, hipStream_t s) {
+    const size_t total = static_cast<size_t>(R) * C;
+    hipLaunchKernelGGL(transpose_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s, in, out,
+                       R, C);
     return hipGetLastError();
 }
 

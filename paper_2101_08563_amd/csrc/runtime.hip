@@ -62,7 +62,7 @@ struct ClassCfg {
 struct MnmfState {
     int K = 0, threads = 0, bpt = 0;
     float *tp = nullptr;    // [F][K][N]
-    float *va = nullptr;    // [T][K][N]
+    float *va = nullptr;    // [K][N][T] (the ABI's [T][K][N] transposed)
     float *G = nullptr, *E = nullptr;  // [F][T][N]
     float *part = nullptr;  // [chunks][2][K][T][N]
     int *vflag = nullptr;
@@ -589,7 +589,7 @@ int fastfca_mnmf_init(fastfca_ctx **out, const fastfca_c64 *x, int F, int T, int
         (rc = dalloc(c, &mn->part, nchunk * 2 * Ks * Ts * Ns)) == FASTFCA_OK &&
         (rc = dalloc(c, &mn->vflag, 1)) == FASTFCA_OK && (rc = dalloc(c, &flag, 2)) == FASTFCA_OK) {
         e = hipMemcpyAsync(mn->tp, t0, sizeof(float) * Fs * Ks * Ns, hipMemcpyDeviceToDevice, c->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(mn->va, v0, sizeof(float) * Ts * Ks * Ns, hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = launch_transpose(v0, mn->va, T, K * N, c->stream);
         if (e == hipSuccess) e = launch_fill_int(mn->vflag, 1, 0, c->stream);
         if (e == hipSuccess) e = launch_fill_int(flag, 2, 0, c->stream);
         if (e == hipSuccess) e = launch_check_positive(mn->tp, Fs * Ks * Ns, flag, c->stream);
@@ -617,7 +617,7 @@ int fastfca_mnmf_get_params(fastfca_ctx *c, fastfca_c128 *P, float *lambda, floa
     if (lambda)
         HIPCHK(c, hipMemcpyAsync(lambda, p.lam, sizeof(float) * F * N * M, hipMemcpyDeviceToDevice, c->stream));
     if (t) HIPCHK(c, hipMemcpyAsync(t, c->mn->tp, sizeof(float) * F * K * N, hipMemcpyDeviceToDevice, c->stream));
-    if (v) HIPCHK(c, hipMemcpyAsync(v, c->mn->va, sizeof(float) * T * K * N, hipMemcpyDeviceToDevice, c->stream));
+    if (v) HIPCHK(c, launch_transpose(c->mn->va, v, static_cast<int>(K * N), static_cast<int>(T), c->stream));
     return FASTFCA_OK;
 }
 
@@ -630,7 +630,7 @@ int fastfca_mnmf_set_params(fastfca_ctx *c, const fastfca_c128 *P, const float *
     if (lambda)
         HIPCHK(c, hipMemcpyAsync(p.lam, lambda, sizeof(float) * F * N * M, hipMemcpyDeviceToDevice, c->stream));
     if (t) HIPCHK(c, hipMemcpyAsync(c->mn->tp, t, sizeof(float) * F * K * N, hipMemcpyDeviceToDevice, c->stream));
-    if (v) HIPCHK(c, hipMemcpyAsync(c->mn->va, v, sizeof(float) * T * K * N, hipMemcpyDeviceToDevice, c->stream));
+    if (v) HIPCHK(c, launch_transpose(v, c->mn->va, static_cast<int>(T), static_cast<int>(K * N), c->stream));
     HIPCHK(c, launch_mnmf_h(c->mn->tp, c->mn->va, p.v, p.F, p.T, p.N, c->mn->K, c->stream));
     HIPCHK(c, launch_fill_int(c->d_status, p.F, ST_OK, c->stream));
     HIPCHK(c, launch_fill_int(c->mn->vflag, 1, 0, c->stream));
