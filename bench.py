@@ -249,12 +249,17 @@ def bench_batch(args):
     stream.synchronize()
     probs = [dict(x=x, N=s["N"]) for x, s in zip(xs, specs)]
     batch = FastFCA.from_batch(probs, seed=1, stream=stream)
-    batch.autotune(n_iter=10)  # launch shape and persistent grid (state is restored)
+    # schedule (class launches or persistent queue), shape and grid; the state is restored
+    import tempfile
+    with tempfile.TemporaryDirectory() as td:
+        cache = os.path.join(td, "tune.jsonl")
+        batch.autotune(n_iter=10, cache_path=cache)
+        with open(cache) as fh:
+            tune = json.loads(fh.read().splitlines()[-1])
     batch.em_step(2)
     batch.sync()
     t_batch = _time(lambda: batch.em_step(iters), stream, max(2, args.steps // 5))
     batch.sync()
-    threads, bpt = batch.get_config()
     batch.close()
     singles = [FastFCA(x, s["N"], seed=1 + i, stream=stream) for i, (x, s) in enumerate(zip(xs, specs))]
     for c in singles:
@@ -275,8 +280,9 @@ def bench_batch(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
            "config": {"workload": "batch: 256 mixtures, T~U{200..2000}, M in {2,3,4}, N in {M+1,M+2}, F=513, "
-                                  "%d IP+EM iterations, one persistent launch" % iters,
-                      "iters": iters, "tf_bins": bins, "threads": threads, "bins_per_thread": bpt,
+                                  "%d IP+EM iterations, %s" % (iters, "one persistent launch" if tune["persistent"]
+                                                               else "one launch per (M, N, T-bucket) class"),
+                      "iters": iters, "tf_bins": bins, "autotune": tune,
                       "sequential_ms": t_seq, "speedup_vs_sequential": t_seq / t_batch,
                       "sequential_updates_per_s": updates / (t_seq * 1e-3)}}
     print(json.dumps(out))

@@ -259,6 +259,20 @@ enum {
  */
 int fastfca_set_algorithm(fastfca_ctx *c, int algo);
 
+/* Schedule of a batch context's fastfca_em_step. */
+enum {
+    FASTFCA_SCHEDULE_CLASSES = 0,    /* one launch per (M, N, T-bucket) class, workgroups sized to T */
+    FASTFCA_SCHEDULE_PERSISTENT = 1  /* one persistent launch over a longest-first work queue */
+};
+
+/*
+ * fastfca_set_schedule -- choose how a batch context iterates (both give the
+ * same results up to the launch shape's summation order). fastfca_autotune
+ * times both and keeps the faster. E_UNSUPPORTED for the persistent schedule
+ * on a single mixture or a batch with classes outside its compiled set.
+ */
+int fastfca_set_schedule(fastfca_ctx *c, int schedule);
+
 /* Launch configuration in effect for the (M,N) class of mixture b. */
 int fastfca_get_config(const fastfca_ctx *c, int b, int *threads, int *bins_per_thread);
 

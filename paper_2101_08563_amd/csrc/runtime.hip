@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -52,6 +53,7 @@ struct Problem {
 
 struct ClassCfg {
     int M, N, Tmax;
+    int bucket = 0;     // batches: workgroup size of a 4-bins-per-thread launch for T (0: one class per (M, N))
     bool cov = false;   // bins carry block covariances (piecewise stationary model)
     bool wide = false;  // wide family (x re-read per iteration) instead of resident
     int threads = 0, bpt = 0;
@@ -73,6 +75,12 @@ struct MnmfState {
 struct fastfca_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    // side streams (default priority) over which the class launches of a
+    // batch are spread so that one class fills the tail of another; forked
+    // from and joined back into `stream` with events (also inside a capture)
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[kSide] = {nullptr, nullptr, nullptr};
     std::vector<Problem> probs;
     std::vector<WorkItem> h_items;
     WorkItem *d_items = nullptr;      // in launch order (grouped by class)
@@ -206,16 +214,24 @@ int validate_shape(fastfca_ctx *c, int F, int T, int M, int N) {
 
 // Builds classes, item order, device item array. Assumes problem buffers exist.
 int build_items(fastfca_ctx *c) {
-    std::map<std::pair<int, int>, int> cls_of;
+    // A class is one (M, N) kernel instantiation; in a batch, mixtures are
+    // further grouped by T so that each class launch has a workgroup sized to
+    // its frames (a mixture with T = 200 does not run in a 512-thread block).
+    std::map<std::tuple<int, int, int>, int> cls_of;
+    auto key_of = [&](const Problem &p) {
+        const int bucket = (c->probs.size() > 1 && !p.blocks && use_resident(p.M, p.N, p.T)) ? threads_for(p.T, 4) : 0;
+        return std::make_tuple(p.M, p.N + (p.blocks ? 1000 : 0), bucket);
+    };
     c->classes.clear();
     for (auto &p : c->probs) {
-        auto key = std::make_pair(p.M, p.N + (p.blocks ? 1000 : 0));
+        auto key = key_of(p);
         if (!cls_of.count(key)) {
             cls_of[key] = static_cast<int>(c->classes.size());
             ClassCfg cc;
             cc.M = p.M;
             cc.N = p.N;
             cc.cov = p.blocks;
+            cc.bucket = std::get<2>(key);
             cc.Tmax = 0;
             c->classes.push_back(cc);
         }
@@ -230,7 +246,7 @@ int build_items(fastfca_ctx *c) {
     c->h_items.assign(total, WorkItem{});
     for (size_t b = 0; b < c->probs.size(); ++b) {
         auto &p = c->probs[b];
-        const int cls = cls_of[std::make_pair(p.M, p.N + (p.blocks ? 1000 : 0))];
+        const int cls = cls_of[key_of(p)];
         for (int f = 0; f < p.F; ++f) {
             WorkItem w{};
             w.x = p.x + static_cast<size_t>(f) * p.T * p.B * p.M;
@@ -424,6 +440,15 @@ int create(fastfca_ctx **out, int B, const fastfca_problem *probs, uint64_t seed
     }
     if (rc == FASTFCA_OK) rc = build_items(c);
     if (rc == FASTFCA_OK) {
+        // batches: side streams for the class schedule (the default); the
+        // persistent queue is kept ready as the alternative the autotuner times
+        if (B > 1) {
+            bool ok = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) == hipSuccess;
+            for (int q = 0; q < fastfca_ctx::kSide && ok; ++q)
+                ok = hipStreamCreateWithFlags(&c->side[q], hipStreamNonBlocking) == hipSuccess &&
+                     hipEventCreateWithFlags(&c->join[q], hipEventDisableTiming) == hipSuccess;
+            if (!ok) rc = set_err(c, FASTFCA_E_HIP, "could not create the side streams of a batch");
+        }
         c->persistent = B > 1;
         if (c->persistent) {
             // one persistent launch: the widest class sets the block shape
@@ -433,15 +458,21 @@ int create(fastfca_ctx **out, int B, const fastfca_problem *probs, uint64_t seed
                 Tmax = std::max(Tmax, cc.Tmax);
                 ok = ok && !cc.wide && persistent_supported(cc.M, cc.N);
             }
-            if (!ok || !pick_default(Tmax, c->p_threads, c->p_bpt)) c->persistent = false;
-            if (c->persistent && c->p_bpt == 2) c->p_bpt = 4;
-            int ncu = 256;
-            if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) !=
-                hipSuccess)
-                ncu = 256;
-            c->p_grid = ncu * std::max(1, 2048 / c->p_threads);
+            if (!ok || !pick_default(Tmax, c->p_threads, c->p_bpt)) {
+                c->persistent = false;
+                c->p_threads = 0;
+            }
+            if (c->persistent) {
+                if (c->p_bpt == 2) c->p_bpt = 4;
+                int ncu = 256;
+                if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) !=
+                    hipSuccess)
+                    ncu = 256;
+                c->p_grid = ncu * std::max(1, 2048 / c->p_threads);
+            }
         }
-        rc = upload_items(c, 128);
+        c->persistent = false;
+        if (rc == FASTFCA_OK) rc = upload_items(c, 128);
     }
     if (rc == FASTFCA_OK) {
         hipError_t e = hipStreamSynchronize(c->stream);
@@ -495,16 +526,39 @@ int record_em(fastfca_ctx *c, int n_iter) {
         HIPCHK(c, launch_em_persistent(a, c->p_threads, c->p_bpt, c->p_grid, c->stream));
         return FASTFCA_OK;
     }
-    for (size_t k = 0; k < c->classes.size(); ++k) {
+    // classes in decreasing total cost, spread round-robin over the context
+    // stream and the side streams when there are several
+    const int ncls = static_cast<int>(c->classes.size());
+    std::vector<int> order(ncls);
+    for (int k = 0; k < ncls; ++k) order[k] = k;
+    auto cost = [&](int k) {
         const auto &cc = c->classes[k];
+        return static_cast<double>(cc.items.size()) * cc.Tmax * (cc.M + cc.N);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    const int nstreams = (ncls > 1 && c->side[0]) ? 1 + fastfca_ctx::kSide : 1;
+    if (nstreams > 1) {
+        HIPCHK(c, hipEventRecord(c->fork, c->stream));
+        for (int q = 0; q < fastfca_ctx::kSide; ++q) HIPCHK(c, hipStreamWaitEvent(c->side[q], c->fork, 0));
+    }
+    for (int r = 0; r < ncls; ++r) {
+        const int k = order[r];
+        const auto &cc = c->classes[k];
+        hipStream_t st = (r % nstreams) == 0 ? c->stream : c->side[(r % nstreams) - 1];
         EmLaunch a{c->d_items + c->class_first[k], static_cast<int>(cc.items.size()), n_iter,
                    nullptr, c->algo};
         if (cc.wide)
             HIPCHK(c, launch_em_wide(cc.M, cc.N, cc.bpt, cc.threads, a,
-                                     static_cast<int>(cc.items.size()), c->stream));
+                                     static_cast<int>(cc.items.size()), st));
         else
             HIPCHK(c, launch_em(cc.M, cc.N, cc.bpt, cc.threads, a, static_cast<int>(cc.items.size()),
-                                c->stream, cc.cov));
+                                st, cc.cov));
+    }
+    if (nstreams > 1) {
+        for (int q = 0; q < fastfca_ctx::kSide; ++q) {
+            HIPCHK(c, hipEventRecord(c->join[q], c->side[q]));
+            HIPCHK(c, hipStreamWaitEvent(c->stream, c->join[q], 0));
+        }
     }
     return FASTFCA_OK;
 }
@@ -831,6 +885,24 @@ int fastfca_set_algorithm(fastfca_ctx *c, int algo) {
     return FASTFCA_OK;
 }
 
+int fastfca_set_schedule(fastfca_ctx *c, int schedule) {
+    if (!c) return FASTFCA_E_ARG;
+    if (schedule != FASTFCA_SCHEDULE_CLASSES && schedule != FASTFCA_SCHEDULE_PERSISTENT)
+        return set_err(c, FASTFCA_E_ARG, "unknown schedule %d", schedule);
+    if (c->mn) return set_err(c, FASTFCA_E_STATE, "FastMNMF contexts use a fixed schedule");
+    const bool want = schedule == FASTFCA_SCHEDULE_PERSISTENT;
+    if (want == c->persistent) return FASTFCA_OK;
+    if (want) {
+        if (c->probs.size() < 2 || !c->p_threads)
+            return set_err(c, FASTFCA_E_UNSUPPORTED, "the persistent schedule needs a batch of supported classes");
+    }
+    int rc = fastfca_sync(c);
+    if (rc != FASTFCA_OK) return rc;
+    c->persistent = want;
+    drop_graph(c);
+    return upload_items(c, c->trace_cap);
+}
+
 int fastfca_get_config(const fastfca_ctx *c, int b, int *threads, int *bins_per_thread) {
     if (!c || b < 0 || b >= static_cast<int>(c->probs.size())) return FASTFCA_E_ARG;
     if (c->persistent) {
@@ -838,14 +910,10 @@ int fastfca_get_config(const fastfca_ctx *c, int b, int *threads, int *bins_per_
         if (bins_per_thread) *bins_per_thread = c->p_bpt;
         return FASTFCA_OK;
     }
-    const auto &p = c->probs[b];
-    for (const auto &cc : c->classes)
-        if (cc.M == p.M && cc.N == p.N && cc.cov == p.blocks) {
-            if (threads) *threads = cc.threads;
-            if (bins_per_thread) *bins_per_thread = cc.bpt;
-            return FASTFCA_OK;
-        }
-    return FASTFCA_E_STATE;
+    const auto &cc = c->classes[c->h_items[c->probs[b].item0].cls];
+    if (threads) *threads = cc.threads;
+    if (bins_per_thread) *bins_per_thread = cc.bpt;
+    return FASTFCA_OK;
 }
 
 int fastfca_autotune(fastfca_ctx *c, int n_iter, const char *cache_path) {
@@ -920,40 +988,53 @@ int fastfca_autotune(fastfca_ctx *c, int n_iter, const char *cache_path) {
         while (b < T) b <<= 1;
         return b;
     };
-    if (c->persistent) {
-        int ncu = 256;
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (c->probs.size() > 1) {
+        // batch: the class schedule at its default shapes against the
+        // persistent queue at each admissible shape and grid
         int Tmax = 0;
         for (auto &cc : c->classes) Tmax = std::max(Tmax, cc.Tmax);
+        float cls_ms = 1e30f, best = 1e30f;
+        c->persistent = false;
+        rc = upload_items(c, c->trace_cap);
+        if (rc == FASTFCA_OK) rc = best_of(cls_ms);
         int bt = c->p_threads, bb = c->p_bpt, bg = c->p_grid;
-        float best = 1e30f;
-        for (int bpt : {4, 8}) {
-            const int th = threads_for(Tmax, bpt);
-            if (!th) continue;
-            for (int per_cu : {1, 2, 4}) {
-                c->p_threads = th;
-                c->p_bpt = bpt;
-                c->p_grid = ncu * per_cu;
-                float ms;
-                rc = best_of(ms);
-                if (rc != FASTFCA_OK) break;
-                if (ms < best) {
-                    best = ms;
-                    bt = th;
-                    bb = bpt;
-                    bg = c->p_grid;
+        if (rc == FASTFCA_OK && c->p_threads) {
+            int ncu = 256;
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+            c->persistent = true;
+            rc = upload_items(c, c->trace_cap);
+            for (int bpt : {4, 8}) {
+                const int th = threads_for(Tmax, bpt);
+                if (!th || rc != FASTFCA_OK) continue;
+                for (int per_cu : {1, 2, 4}) {
+                    c->p_threads = th;
+                    c->p_bpt = bpt;
+                    c->p_grid = ncu * per_cu;
+                    float ms;
+                    rc = best_of(ms);
+                    if (rc != FASTFCA_OK) break;
+                    if (ms < best) {
+                        best = ms;
+                        bt = th;
+                        bb = bpt;
+                        bg = c->p_grid;
+                    }
                 }
             }
-            if (rc != FASTFCA_OK) break;
+            c->p_threads = bt;
+            c->p_bpt = bb;
+            c->p_grid = bg;
         }
-        c->p_threads = bt;
-        c->p_bpt = bb;
-        c->p_grid = bg;
+        if (rc == FASTFCA_OK) {
+            c->persistent = best < cls_ms;
+            rc = upload_items(c, c->trace_cap);
+        }
         if (cache && rc == FASTFCA_OK)
             fprintf(cache,
-                    "{\"arch\": \"%s\", \"kind\": \"persistent\", \"items\": %zu, \"Tbucket\": %d, "
-                    "\"threads\": %d, \"bins_per_thread\": %d, \"grid\": %d, \"ms\": %.6f}\n",
-                    c->arch, c->h_items.size(), bucket(Tmax), bt, bb, bg, best);
+                    "{\"arch\": \"%s\", \"kind\": \"batch\", \"items\": %zu, \"Tbucket\": %d, "
+                    "\"class_launches_ms\": %.6f, \"persistent_ms\": %.6f, \"threads\": %d, "
+                    "\"bins_per_thread\": %d, \"grid\": %d, \"persistent\": %d}\n",
+                    c->arch, c->h_items.size(), bucket(Tmax), cls_ms, best, bt, bb, bg, c->persistent ? 1 : 0);
     } else {
         for (auto &cc : c->classes) {
             int bt = cc.threads, bb = cc.bpt;
@@ -1022,6 +1103,14 @@ void fastfca_destroy(fastfca_ctx *c) {
     if (!c) return;
     if (c->stream) hipStreamSynchronize(c->stream);
     drop_graph(c);
+    for (int q = 0; q < fastfca_ctx::kSide; ++q) {
+        if (c->side[q]) {
+            hipStreamSynchronize(c->side[q]);
+            hipStreamDestroy(c->side[q]);
+        }
+        if (c->join[q]) hipEventDestroy(c->join[q]);
+    }
+    if (c->fork) hipEventDestroy(c->fork);
     for (auto &p : c->probs) free_problem(p);
     if (c->mn) {
         hipFree(c->mn->tp);

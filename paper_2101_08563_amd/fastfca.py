@@ -39,6 +39,7 @@ SIGNATURES = {
     "fastfca_autotune": (_i, [_vp, _i, ctypes.c_char_p]),
     "fastfca_get_config": (_i, [_vp, _i, _pi, _pi]),
     "fastfca_set_algorithm": (_i, [_vp, _i]),
+    "fastfca_set_schedule": (_i, [_vp, _i]),
     "fastfca_init_blocks": (_i, [ctypes.POINTER(_vp), _vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _u64, _vp]),
     "fastfca_block_length": (_i, [_vp, _i]),
     "fastfca_mnmf_init": (_i, [ctypes.POINTER(_vp), _vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]),
@@ -304,6 +305,11 @@ class FastFCA:
         """'em' (Algorithm 1, default) or 'mm' (Algorithm 2)."""
         code = {"em": 0, "mm": 1}[algo] if isinstance(algo, str) else int(algo)
         self._chk(self._lib.fastfca_set_algorithm(self._ctx, code))
+
+    def set_schedule(self, schedule):
+        """Batches: 'classes' (one launch per (M, N, T-bucket) class) or 'persistent'."""
+        code = {"classes": 0, "persistent": 1}[schedule] if isinstance(schedule, str) else int(schedule)
+        self._chk(self._lib.fastfca_set_schedule(self._ctx, code))
 
     def get_config(self, b=0):
         th, bpt = ctypes.c_int(), ctypes.c_int()

@@ -44,9 +44,11 @@ def test_batch_shapes_cover_the_classes():
     assert 200 <= min(Ts) and max(Ts) <= 2000
 
 
-def test_batch_matches_oracle_per_mixture():
+@pytest.mark.parametrize("schedule", ["persistent", "classes"])
+def test_batch_matches_oracle_per_mixture(schedule):
     inputs = batch_inputs(8, F=12)
     ctx, _ = make_batch(inputs)
+    ctx.set_schedule(schedule)
     assert ctx.num_problems == 8
     ctx.em_step(20)
     ctx.sync()
@@ -55,7 +57,7 @@ def test_batch_matches_oracle_per_mixture():
         Po, lo, vo, tro = oracle.fit(x, P0, lam0, v0, 20, trace=True)
         llo, _ = oracle.loglik(x, Po, lo, vo)
         errs = dict(v=rel(v, vo), lam=rel(lam, lo), P=rel(P, Po), ll=abs(ctx.loglik(b) - llo))
-        print("mixture", b, x.shape, N, errs, flush=True)
+        print(schedule, "mixture", b, x.shape, N, errs, flush=True)
         assert errs["v"] < 1e-4 and errs["lam"] < 1e-4 and errs["P"] < 1e-4 and errs["ll"] < 1e-6, errs
         tr = ctx.ll_trace(b)
         assert np.abs(tr - tro).max() < 1e-4
