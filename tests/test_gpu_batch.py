@@ -133,3 +133,27 @@ def test_single_autotune_cache(tmp_path):
     Po, lo, vo, _ = oracle.fit(x, P0, lam0, v0, 6)
     assert rel(ctx.get_params()[2].cpu().numpy(), vo) < 1e-4
     ctx.close()
+
+
+def test_batch_with_a_wide_class_uses_class_launches():
+    """A batch holding a mixture outside the persistent kernel's classes (M = 5:
+    the wide family) runs with the class schedule; the persistent schedule is
+    refused; every mixture matches the oracle."""
+    from paper_2101_08563_amd import FastFCAError
+    shapes = [(5, 300, 5, 6), (7, 650, 2, 3), (6, 130, 3, 5)]
+    inputs = []
+    for i, (F, T, M, N) in enumerate(shapes):
+        x = synth.mixture(F=F, T=T, M=M, N=N, rank=3, config_id=45, mixture_id=i)
+        P0, lam0, v0 = synth.init_params(x, N, config_id=45, mixture_id=i)
+        inputs.append((x, P0, lam0, v0, N))
+    ctx, _ = make_batch(inputs)
+    with pytest.raises(FastFCAError) as e:
+        ctx.set_schedule("persistent")
+    assert e.value.code == -7
+    ctx.em_step(10)
+    ctx.sync()
+    for b, (x, P0, lam0, v0, N) in enumerate(inputs):
+        P, lam, v = (t.cpu().numpy() for t in ctx.get_params(b))
+        Po, lo, vo, _ = oracle.fit(x, P0, lam0, v0, 10)
+        assert rel(v, vo) < 1e-4 and rel(lam, lo) < 1e-4 and rel(P, Po) < 1e-4
+    ctx.close()

@@ -31,7 +31,8 @@ def case(F, T, M, N, B, cid):
 
 
 @pytest.mark.parametrize("M,N,B,T,algo", [(2, 3, 4, 1000, 0), (3, 4, 8, 1600, 0), (4, 6, 5, 1000, 0),
-                                          (2, 2, 3, 231, 0), (2, 3, 4, 1000, 1), (3, 5, 2, 770, 1)])
+                                          (2, 2, 3, 231, 0), (2, 3, 4, 1000, 1), (3, 5, 2, 770, 1),
+                                          (2, 8, 2, 4096, 0), (4, 3, 16, 96, 0)])
 def test_block_model_parity(M, N, B, T, algo):
     F, iters = 9, 25
     x, P0, lam0, v0 = case(F, T, M, N, B, 60 + M)

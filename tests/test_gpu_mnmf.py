@@ -26,7 +26,7 @@ def dev(*arrs):
 
 
 @pytest.mark.parametrize("M,N,K,F,T", [(2, 3, 4, 33, 400), (3, 4, 8, 17, 300), (4, 5, 2, 9, 250),
-                                       (2, 6, 16, 13, 500), (2, 2, 1, 70, 129)])
+                                       (2, 6, 16, 13, 500), (2, 2, 1, 70, 129), (3, 3, 32, 40, 2000)])
 def test_fastmnmf_parity(M, N, K, F, T):
     iters = 15
     x = synth.mixture(F=F, T=T, M=M, N=N, rank=8, diffuse=0.05, config_id=95, mixture_id=K)
