@@ -33,13 +33,17 @@ FP32_FMA_PEAK = CU * SIMD_PER_CU * LANES * 2 * CLOCK_HZ      # 78.6 TFLOP/s, non
 HBM_PEAK = 8.0e12                                            # bytes/s
 
 
-def em_flops_per_bin(M: int, N: int) -> int:
-    """Algorithmic flops per TF bin per IP+EM iteration (FMA = 2 flops):
+def em_flops_per_bin(M: int, N: int, algo: str = "em") -> int:
+    """Algorithmic flops per TF bin per iteration (FMA = 2 flops):
     sigma^2 and its inverse (2MN + M), x x^H as M^2 real parameters (3M^2),
-    the M weighted covariances (2M^3), U = |P^H x|^2 (8M^2 + 3M), the N
-    sequential source updates (N (2MN + 12M + 2)), the log-likelihood terms (4M)."""
-    return (2 * M * N + M) + 3 * M * M + 2 * M ** 3 + (8 * M * M + 3 * M) \
-        + N * (2 * M * N + 12 * M + 2) + 4 * M
+    the M weighted covariances (2M^3), U = |P^H x|^2 (8M^2 + 3M), the
+    log-likelihood terms (4M), and the L/H update: for IP+EM the N sequential
+    source updates (N (2MN + 12M + 2)); for IP+MM the L-rule sums (2MN + 3M
+    + 4NM) and the H rule (2MN + 3M + 4NM + 3N)."""
+    common = (2 * M * N + M) + 3 * M * M + 2 * M ** 3 + (8 * M * M + 3 * M) + 4 * M
+    if algo == "mm":
+        return common + 2 * (2 * M * N + 3 * M + 4 * N * M) + 3 * N
+    return common + N * (2 * M * N + 12 * M + 2)
 
 
 def em_bytes_per_bin(M: int, N: int) -> int:
@@ -81,6 +85,8 @@ def main():
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttc", action="store_true", help="skip the time-to-converge comparison")
+    ap.add_argument("--algo", choices=["em", "mm"], default="em",
+                    help="headline update: Algorithm 1 (IP+EM, the contract line) or Algorithm 2 (IP+MM)")
     ap.add_argument("--calib-copy", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--bpt", type=int, default=0)
@@ -126,6 +132,8 @@ def main():
         y = torch.empty((N, F, T, M), dtype=torch.complex64, device=dev)
     stream.synchronize()
     ctx = FastFCA(xd, N, Pd, ld, vd, stream=stream)
+    if args.algo == "mm":
+        ctx.set_algorithm("mm")
     if args.threads:
         ctx.set_config(args.threads, args.bpt)
     threads, bpt = ctx.get_config()
@@ -159,7 +167,7 @@ def main():
 
     updates = F * T * N * iters
     value = updates / (ms_per_step * 1e-3)
-    flops = em_flops_per_bin(M, N) * F * T * iters
+    flops = em_flops_per_bin(M, N, args.algo) * F * T * iters
     achieved = flops / (em_ms * 1e-3)
     hbm_bytes = em_bytes_per_bin(M, N) * F * T
     out = {
@@ -175,17 +183,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "FastFCA IP+EM x%d + MWF, M=%d N=%d F=%d T=%d" % (iters, M, N, F, T),
+        "config": {"workload": "FastFCA IP+%s x%d + MWF, M=%d N=%d F=%d T=%d" % (args.algo.upper(), iters, M, N, F, T),
                    "M": M, "N": N, "F": F, "T": T, "iters": iters, "threads": threads,
                    "bins_per_thread": bpt, "ll_per_bin": ll},
         "roofline": {
-            "kernel": "em_kernel<%d,%d,%d> (IP+EM, state resident on chip)" % (M, N, bpt),
+            "kernel": "em_kernel<%d,%d,%d> (IP+%s, state resident on chip)" % (M, N, bpt, args.algo.upper()),
             "bound": "alu",
             "achieved": achieved / 1e12,
             "peak": FP32_FMA_PEAK / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_FMA_PEAK,
-            "traffic": measured_traffic() if iters == 100 else None,
+            "traffic": measured_traffic() if (iters == 100 and args.algo == "em") else None,
             "em_ms_per_launch": em_ms,
             "flops_per_launch": flops,
             "hbm_algorithmic_bytes_per_launch": hbm_bytes,
@@ -381,13 +389,27 @@ def bench_blocks(args, B=4):
     ctx.close()
     J = T // B
     updates = F * J * N * iters
-    print(json.dumps({"metric": "EM TF-bin*source updates/s", "value": updates / (t * 1e-3), "unit": "updates/s",
-                      "n_gpus": 1, "steps": max(3, args.steps // 4), "warmup": 1, "ms_per_step": t,
-                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-                      "data": "synthetic",
-                      "config": {"workload": "piecewise stationary model, blocks of %d frames: M=%d N=%d F=%d "
-                                             "T=%d (J=%d blocks), %d IP+EM iterations" % (B, M, N, F, T, J, iters),
-                                 "frames_per_s": F * T * iters / (t * 1e-3)}}))
+    # flops per block and iteration: as em_flops_per_bin, with Q_m taking the
+    # block covariance directly (2M^3) and U a dot product of its M^2 parameters (2M^3)
+    fl = (2 * M * N + M) + 2 * M ** 3 + 2 * M ** 3 + N * (2 * M * N + 12 * M + 2) + 4 * M
+    out = {"metric": "EM TF-bin*source updates/s", "value": updates / (t * 1e-3), "unit": "updates/s",
+           "n_gpus": 1, "steps": max(3, args.steps // 4), "warmup": 1, "ms_per_step": t,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "piecewise stationary model, blocks of %d frames: M=%d N=%d F=%d "
+                                  "T=%d (J=%d blocks), %d IP+EM iterations" % (B, M, N, F, T, J, iters),
+                      "frames_per_s": F * T * iters / (t * 1e-3)},
+           "roofline": {"bound": "alu", "achieved": fl * F * J * iters / (t * 1e-3) / 1e12,
+                        "peak": FP32_FMA_PEAK / 1e12, "unit": "TFLOP/s",
+                        "frac": fl * F * J * iters / (t * 1e-3) / FP32_FMA_PEAK, "traffic": None}}
+    if not args.no_cpu:
+        import oracle
+        t2 = time.perf_counter()
+        oracle.fit_blocks(x, B, P0, lam0, v0, iters)
+        t3 = time.perf_counter()
+        out["cpu_baseline"] = {"value": updates / (t3 - t2), "unit": "updates/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": "full workload, %d iterations, %.2f s" % (iters, t3 - t2)}
+    print(json.dumps(out))
 
 
 def bench_mnmf(args, K=8):
@@ -419,14 +441,26 @@ def bench_mnmf(args, K=8):
     ctx.close()
     updates = F * T * N * iters
     hbm = (8 * M + 16 * N) * F * T * iters   # x read; G, E written and read back, per iteration
-    print(json.dumps({"metric": "EM TF-bin*source updates/s", "value": updates / (t * 1e-3), "unit": "updates/s",
-                      "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": t, "higher_is_better": True,
-                      "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-                      "config": {"workload": "FastMNMF: M=%d N=%d K=%d F=%d T=%d, %d IP+MM iterations"
-                                             % (M, N, K, F, T, iters), "ll_per_bin": ll,
-                                 "us_per_iteration": t * 1e3 / iters},
-                      "roofline": {"bound": "hbm", "achieved": hbm / (t * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
-                                   "unit": "GB/s", "frac": hbm / (t * 1e-3) / HBM_PEAK, "traffic": None}}))
+    out = {"metric": "EM TF-bin*source updates/s", "value": updates / (t * 1e-3), "unit": "updates/s",
+           "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": t, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "FastMNMF: M=%d N=%d K=%d F=%d T=%d, %d IP+MM iterations"
+                                  % (M, N, K, F, T, iters), "ll_per_bin": ll,
+                      "us_per_iteration": t * 1e3 / iters},
+           "roofline": {"bound": "hbm", "achieved": hbm / (t * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
+                        "unit": "GB/s", "frac": hbm / (t * 1e-3) / HBM_PEAK, "traffic": None}}
+    if not args.no_cpu:
+        # the oracle (single thread: the frequencies are coupled through V) on
+        # the first 64 frequencies for 5 iterations, scaled to updates/s
+        import oracle
+        Fs, its = 64, 5
+        t2 = time.perf_counter()
+        oracle.mnmf_fit(x[:Fs], P0[:Fs], lam0[:Fs], t0[:Fs], v0, its)
+        t3 = time.perf_counter()
+        out["cpu_baseline"] = {"value": Fs * T * N * its / (t3 - t2), "unit": "updates/s", "cores": 1,
+                               "kind": "oracle", "sample": "F=%d of %d frequencies, %d iterations, %.2f s"
+                                                           % (Fs, F, its, t3 - t2)}
+    print(json.dumps(out))
 
 
 if __name__ == "__main__":
