@@ -451,9 +451,9 @@ def bench_mnmf(args, K=8):
                         "unit": "GB/s", "frac": hbm / (t * 1e-3) / HBM_PEAK, "traffic": None}}
     if not args.no_cpu:
         # the oracle (single thread: the frequencies are coupled through V) on
-        # the first 64 frequencies for 5 iterations, scaled to updates/s
+        # the full mixture for 5 iterations
         import oracle
-        Fs, its = 64, 5
+        Fs, its = F, 5
         t2 = time.perf_counter()
         oracle.mnmf_fit(x[:Fs], P0[:Fs], lam0[:Fs], t0[:Fs], v0, its)
         t3 = time.perf_counter()
