@@ -339,6 +339,20 @@ def bench_large(args):
     t = _time(lambda: ctx.em_step(iters), stream, 3)
     threads, bpt = ctx.get_config()
     ll = ctx.loglik()
+    cpu = None
+    if not args.no_cpu:
+        # the oracle on 64 of the frequencies for 2 iterations from the library's init
+        import oracle
+        Fs, its = 64, 2
+        ctx2 = FastFCA(x[:Fs].contiguous(), N, seed=3, stream=stream)
+        P0, l0, v0 = (a.cpu().numpy() for a in ctx2.get_params())
+        xs = x[:Fs].cpu().numpy()
+        ctx2.close()
+        t2 = time.perf_counter()
+        oracle.fit(xs, P0, l0, v0, its)
+        t3 = time.perf_counter()
+        cpu = {"value": Fs * T * N * its / (t3 - t2), "unit": "updates/s", "cores": oracle.num_threads(),
+               "kind": "oracle", "sample": "F=%d of %d frequencies, %d iterations, %.2f s" % (Fs, F, its, t3 - t2)}
     ctx.close()
     updates = F * T * N * iters
     flops = em_flops_per_bin(M, N) * F * T * iters
@@ -351,6 +365,8 @@ def bench_large(args):
                         "achieved": flops / (t * 1e-3) / 1e12, "peak": FP32_FMA_PEAK / 1e12, "unit": "TFLOP/s",
                         "frac": flops / (t * 1e-3) / FP32_FMA_PEAK, "traffic": None,
                         "hbm_GBps_algorithmic": (16 * M * iters + 8 * N) * F * T / (t * 1e-3) / 1e9}}
+    if cpu:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 

@@ -227,6 +227,15 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
 
     for (int iter = 0; iter <= n_iter; ++iter) {
         const bool last = (iter == n_iter);
+        if constexpr (!COV && M >= 3) {
+            // x x^H is formed again every iteration instead of being kept
+            // across iterations: for M >= 3 its M^2 values per bin cost more
+            // in occupancy than the 3M^2 operations that recompute them
+#pragma unroll
+            for (int k = 0; k < BPT; ++k)
+#pragma unroll
+                for (int r = 0; r < M; ++r) asm volatile("" : "+v"(xr[k][r].x), "+v"(xr[k][r].y));
+        }
         // ---------------- phase A: weights, Q_m, LL terms of the previous iterate
         float q[NQ];
 #pragma unroll
