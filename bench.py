@@ -90,10 +90,12 @@ def main():
     ap.add_argument("--calib-copy", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--bpt", type=int, default=0)
-    ap.add_argument("--workload", choices=["headline", "batch", "large", "blocks", "mnmf"], default="headline",
+    ap.add_argument("--workload", choices=["headline", "batch", "batch32", "large", "blocks", "mnmf"],
+                    default="headline",
                     help="headline: the contract line (M=2 N=3 F=513 T=1000); batch: 256 mixed "
                          "mixtures in one persistent launch vs sequential runs; large: M=8 N=10 "
-                         "F=1025 T=4000; blocks: the piecewise stationary model on the headline "
+                         "F=1025 T=4000; batch32: 32 headline-shaped mixtures in one context; "
+                         "blocks: the piecewise stationary model on the headline "
                          "mixture (B=4); mnmf: FastMNMF on the headline mixture (K=8)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -106,6 +108,8 @@ def main():
         return bench_batch(args)
     if args.workload == "large":
         return bench_large(args)
+    if args.workload == "batch32":
+        return bench_batch32(args)
     if args.workload == "blocks":
         return bench_blocks(args)
     if args.workload == "mnmf":
@@ -319,6 +323,43 @@ def bench_batch(args):
                       "sequential_ms": t_seq, "speedup_vs_sequential": t_seq / t_batch,
                       "sequential_updates_per_s": updates / (t_seq * 1e-3)}}
     print(json.dumps(out))
+
+
+def bench_batch32(args, B=32):
+    """B mixtures of the headline shape (M=2 N=3 F=513 T=1000, different seeds)
+    in one context: the same kernel as the headline line, with enough
+    workgroups (B x 513) that no CU runs a third frequency alone at the end."""
+    import torch
+
+    from paper_2101_08563_amd import FastFCA
+    from paper_2101_08563_amd.fastfca import synth_mixture
+
+    F, T, M, N, iters = 513, 1000, 2, 3, args.iters
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        xs = [synth_mixture(F, T, M, N, rank=8, diffuse=0.05, seed=500 + i, stream=stream) for i in range(B)]
+    stream.synchronize()
+    ctx = FastFCA.from_batch([dict(x=x, N=N) for x in xs], seed=5, stream=stream)
+    ctx.em_step(2)
+    ctx.sync()
+    reps = max(3, args.steps // 4)
+    t = _time(lambda: ctx.em_step(iters), stream, reps)
+    ctx.sync()
+    threads, bpt = ctx.get_config()
+    ctx.close()
+    updates = B * F * T * N * iters
+    flops = em_flops_per_bin(M, N) * B * F * T * iters
+    single_pass = (8 * M + 8 * N) * B * F * T * iters  # one HBM pass per iteration (x read, v read and written)
+    print(json.dumps({"metric": "EM TF-bin*source updates/s", "value": updates / (t * 1e-3), "unit": "updates/s",
+                      "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": t, "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "%d headline-shaped mixtures (M=2 N=3 F=513 T=1000), %d IP+EM "
+                                             "iterations, one context" % (B, iters),
+                                 "threads": threads, "bins_per_thread": bpt,
+                                 "single_pass_hbm_equivalent_GBps": single_pass / (t * 1e-3) / 1e9},
+                      "roofline": {"kernel": "em_kernel<2,3,%d>" % bpt, "bound": "alu",
+                                   "achieved": flops / (t * 1e-3) / 1e12, "peak": FP32_FMA_PEAK / 1e12,
+                                   "unit": "TFLOP/s", "frac": flops / (t * 1e-3) / FP32_FMA_PEAK, "traffic": None}}))
 
 
 def bench_large(args):
