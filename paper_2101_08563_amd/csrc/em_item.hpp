@@ -8,6 +8,7 @@
 //   LDS       : P in double precision, its single precision copy, reduction
 //               partials
 //   wave 0    : the double precision IP sweep (eq:ip1, eq:ip2) and ln|det P|^2
+//   wave 1    : meanwhile, the log-likelihood of the previous iterate
 // so HBM is touched once per call (read x, h, L, P; write h, L, P). Every
 // T-reduction is a fixed-order wavefront DPP tree followed by a fixed-order
 // sum over waves, so results are bitwise reproducible for a given launch
@@ -57,7 +58,9 @@ struct EmSmem {
     double2 Pd[kMaxM * kMaxM];
     float2 P32[kMaxM * kMaxM];
     IpLds<kMaxM> ip;             // IP scratch (lane-parallel sweep, M = 3, 4)
-    int flag;
+    double ldet[2];              // ln|det P|^2 of the IP of iterations of each parity
+    int flag;                    // IP status
+    int flag_ll;                 // likelihood status
 };
 
 // Fixed-order sum of the NS partials of one value, loaded in chunks of up to
@@ -105,6 +108,60 @@ __device__ __forceinline__ double sum_slots(const double *p) {
     return tot;
 }
 
+// The same fixed-order sums over the populated slots only: the partials of
+// nw waves fill the first 4 nw row slots (first nw wave slots). Slots are
+// summed in groups of four waves (16 row slots, 4 wave slots), each group as
+// a tree and the groups in order; the slots past the last wave hold zeros.
+template <int NS>
+__device__ __forceinline__ float sum_rows(const float *p, int nw) {
+    float tot = 0.0f;
+#pragma unroll
+    for (int g = 0; g < NS / 16; ++g) {
+        if (g == 0 || g * 4 < nw) {
+            float s[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float4 a = *reinterpret_cast<const float4 *>(p + 16 * g + 4 * i);
+                s[i] = (a.x + a.y) + (a.z + a.w);
+            }
+            const float u = (s[0] + s[1]) + (s[2] + s[3]);
+            tot = g == 0 ? u : tot + u;
+        }
+    }
+    return tot;
+}
+template <int NS>
+__device__ __forceinline__ double sum_rows(const double *p, int nw) {
+    double tot = 0.0;
+#pragma unroll
+    for (int g = 0; g < NS / 16; ++g) {
+        if (g == 0 || g * 4 < nw) {
+            double s[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const double2 a = *reinterpret_cast<const double2 *>(p + 16 * g + 2 * i);
+                s[i] = a.x + a.y;
+            }
+            const double u = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+            tot = g == 0 ? u : tot + u;
+        }
+    }
+    return tot;
+}
+template <int NS>
+__device__ __forceinline__ float sum_waves(const float *p, int nw) {
+    float tot = 0.0f;
+#pragma unroll
+    for (int g = 0; g < NS / 4; ++g) {
+        if (g == 0 || g * 4 < nw) {
+            const float4 a = *reinterpret_cast<const float4 *>(p + 4 * g);
+            const float u = (a.x + a.y) + (a.z + a.w);
+            tot = g == 0 ? u : tot + u;
+        }
+    }
+    return tot;
+}
+
 // IP sweep for M = 2 in registers (every lane of wave 0 computes the same
 // values). For 2 x 2 matrices the solve of eq:ip1, w = (P^H Q_m)^{-1} e_m,
 // equals Q_m^{-1} P^{-H} e_m, and both inverses are adjugates over
@@ -118,15 +175,17 @@ __device__ __forceinline__ double sum_slots(const double *p) {
 // taken as singular when |det(P^H Q)|^2 = |d|^2 det(Q)^2 falls below
 // tol^2 (|P|_F^2 |Q|_F^2)^2, the fourth power of a bound on its largest entry.
 // q: the 8 reduced Hermitian parameters (Q_1 then Q_2), already / T.
+// The checks are folded into one status without branches; nothing is
+// stored unless both columns pass.
 template <class Smem>
 __device__ __forceinline__ int ip_sweep_reg2(Smem &sm, const double (&q)[8], double &ldet) {
     cd P00 = ld(sm.Pd[0]), P01 = ld(sm.Pd[1]), P10 = ld(sm.Pd[2]), P11 = ld(sm.Pd[3]);
+    int stat = ST_OK;
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
         const double q00 = q[4 * m + 0], q11 = q[4 * m + 1];
         const cd q01 = cmk(q[4 * m + 2], q[4 * m + 3]);
-        if (!(fabs(q00) < INFINITY) || !(fabs(q11) < INFINITY) || !(abs2(q01) < INFINITY))
-            return ST_NONFINITE;
+        const bool fin = (fabs(q00) < INFINITY) && (fabs(q11) < INFINITY) && (abs2(q01) < INFINITY);
         const cd b0 = m == 0 ? conjd(P11) : cmk(-P10.re, P10.im);
         const cd b1 = m == 0 ? cmk(-P01.re, P01.im) : conjd(P00);
         const cd u0 = q11 * b0 - q01 * b1;
@@ -138,8 +197,8 @@ __device__ __forceinline__ int ip_sweep_reg2(Smem &sm, const double (&q)[8], dou
         const double nq = q00 * q00 + q11 * q11 + 2.0 * abs2(q01);
         const double np = (abs2(P00) + abs2(P01)) + (abs2(P10) + abs2(P11));
         const double t = sb * dq * d2;
-        if (!(d2 * dq * dq >= kPivotTol * kPivotTol * (np * nq) * (np * nq)) || !(t > 0.0) || !(t < INFINITY))
-            return ST_SINGULAR;
+        const bool piv = (d2 * dq * dq >= kPivotTol * kPivotTol * (np * nq) * (np * nq)) && (t > 0.0) && (t < INFINITY);
+        stat = stat != ST_OK ? stat : (!fin ? ST_NONFINITE : (!piv ? ST_SINGULAR : ST_OK));
         const double r = rsqrt_d(t);
         const cd w0 = r * (u0 * d), w1 = r * (u1 * d);
         if (m == 0) {
@@ -150,6 +209,7 @@ __device__ __forceinline__ int ip_sweep_reg2(Smem &sm, const double (&q)[8], dou
             P11 = w1;
         }
     }
+    if (stat != ST_OK) return stat;
     // ln|det P|^2 for the likelihood trace (single precision logarithm)
     ldet = static_cast<double>(ln_fast(static_cast<float>(abs2(P00 * P11 - P01 * P10))));
     sm.Pd[0] = st(P00);
@@ -179,6 +239,8 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
     const int wid = tid >> 6;
     const bool row_lead = (lane & 15) == 0;
     const int row_slot = 4 * wid + (lane >> 4);
+    const int nw = nthr >> 6;
+    const int llw = nw > 1 ? 1 : 0;  // wave that finishes the likelihood while wave 0 runs the IP
     const int T = it.T;
     const float invTf = 1.0f / static_cast<float>(T);
     const double invT = 1.0 / static_cast<double>(T);
@@ -190,6 +252,16 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
     float vr[BPT][N];
     float U[BPT][M];
     float mk[BPT];
+    // M = 2 keeps sigma^2 and 1/sigma^2 of every bin from phase A through
+    // phase C: source 1 uses them as they are, and each later source updates
+    // sigma^2 by the change of its own term (two FMAs instead of N). Phase A
+    // recomputes them from L and H every iteration, so rounding does not
+    // accumulate across iterations. Wider M would lose occupancy to the
+    // 2 M BPT registers (and M = 2 with eight bins per thread beyond four
+    // sources).
+    constexpr bool kKeep = (M == 2) && (BPT <= 4 || N <= 4);
+    float sg[kKeep ? BPT : 1][M];
+    float wr[kKeep ? BPT : 1][M];
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {
         const int t = tid + k * nthr;
@@ -215,13 +287,17 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
     if (tid < M * M) {
         sm.Pd[tid] = it.P[tid];
     }
-    if (tid == 0) sm.flag = ST_OK;
+    if (tid == 0) {
+        sm.flag = ST_OK;
+        sm.flag_ll = ST_OK;
+    }
     for (int i = tid; i < static_cast<int>(sizeof(sm.redq) / sizeof(float)); i += nthr) (&sm.redq[0][0])[i] = 0.0f;
     for (int i = tid; i < static_cast<int>(sizeof(sm.redc) / sizeof(float)); i += nthr) (&sm.redc[0][0][0])[i] = 0.0f;
     for (int i = tid; i < NR; i += nthr) sm.red_d[i] = 0.0;
     __syncthreads();
 
-    double ldet_prev = 0.0;  // ln|det P|^2 of the iterate being evaluated (wave 0)
+    double ldet_prev = 0.0;  // ln|det P|^2 of the latest iterate (wave 0)
+    double *const ll_trace = it.ll_trace;
     int buf = 0;
     int status = ST_OK;
 
@@ -253,6 +329,10 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                 for (int n = 0; n < N; ++n) s = fmaf(vr[k][n], lam[n][m], s);
                 s2[m] = s;
                 w[m] = rcp(s);
+                if constexpr (kKeep) {
+                    sg[k][m] = s;
+                    wr[k][m] = w[m];
+                }
             }
             if (iter > 0) {
                 float l = 0.0f;
@@ -303,37 +383,42 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
             sm.red_d[row_slot] = llp;
         }
         __syncthreads();
-        if (wid == 0) {
-            if (iter > 0) {
-                const double s = sum_slots<NR>(sm.red_d);
-                const double ll = ldet_prev - static_cast<double>(M) * kLnPi - s * invT;
-                if (lane == 0) it.ll_trace[iter - 1] = ll;
-                if (!(ll == ll) || ll == INFINITY || ll == -INFINITY) status = ST_NONFINITE;
+        if (wid == llw && iter > 0) {
+            // eq:negll for the previous iterate, beside the IP on wave 0
+            const double s = sum_rows<NR>(sm.red_d, nw);
+            const double ll = sm.ldet[(iter - 1) & 1] - static_cast<double>(M) * kLnPi - s * invT;
+            if (lane == 0) {
+                ll_trace[iter - 1] = ll;
+                if (!(ll == ll) || ll == INFINITY || ll == -INFINITY) sm.flag_ll = ST_NONFINITE;
             }
-            if (!last && status == ST_OK) {
-                double ldet = 0.0;
-                if constexpr (M == 2) {
-                    // lane i sums value i over the row slots, then every lane
-                    // reads all eight sums from registers
-                    double qs[8];
-                    const float mine = lane < 8 ? sum_slots<NR>(sm.redq[lane]) : 0.0f;
+        }
+        if (wid == 0 && !last) {
+            double ldet = 0.0;
+            if constexpr (M == 2) {
+                // lane i sums value i over the row slots, then every lane
+                // reads all eight sums from registers
+                double qs[8];
+                const float mine = lane < 8 ? sum_rows<NR>(sm.redq[lane], nw) : 0.0f;
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) qs[i] = static_cast<double>(readlane_f(mine, i)) * invT;
-                    status = ip_sweep_reg2(sm, qs, ldet);
-                } else {
-                    if (lane < NQ) sm.qtot[lane] = static_cast<double>(sum_slots<NR>(sm.redq[lane])) * invT;
-                    __threadfence_block();
-                    __builtin_amdgcn_wave_barrier();
-                    // lane-parallel IP sweep in double precision
-                    status = ip_wave<M, kMaxM>(sm.qtot, sm.Pd, sm.P32, sm.ip, ldet);
-                }
-                if (status == ST_OK) ldet_prev = ldet;
+                for (int i = 0; i < 8; ++i) qs[i] = static_cast<double>(readlane_f(mine, i)) * invT;
+                status = ip_sweep_reg2(sm, qs, ldet);
+            } else {
+                if (lane < NQ) sm.qtot[lane] = static_cast<double>(sum_rows<NR>(sm.redq[lane], nw)) * invT;
+                __threadfence_block();
+                __builtin_amdgcn_wave_barrier();
+                // lane-parallel IP sweep in double precision
+                status = ip_wave<M, kMaxM>(sm.qtot, sm.Pd, sm.P32, sm.ip, ldet);
+            }
+            if (status == ST_OK) {
+                ldet_prev = ldet;
+                if (lane == 0) sm.ldet[iter & 1] = ldet;
             }
             if (lane == 0) sm.flag = status;
         }
         if (last) break;
         __syncthreads();
         status = sm.flag;
+        if (status == ST_OK) status = sm.flag_ll;
         if (status != ST_OK) break;
 
         // ---------------- phase B: U = |P^H x|^2, or w_m^H Xhat w_m
@@ -419,7 +504,7 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                 for (int i = 0; i < 2 * N * M; ++i) sm.redc[buf][i][wid] = nd[i];
             }
             __syncthreads();
-            const float mine = lane < 2 * N * M ? sum_slots<NW>(sm.redc[buf][lane]) : 0.0f;
+            const float mine = lane < 2 * N * M ? sum_waves<NW>(sm.redc[buf][lane], nw) : 0.0f;
             bool good = true;
 #pragma unroll
             for (int n = 0; n < N; ++n)
@@ -473,19 +558,26 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
             float part[M];
             float e[BPT][M];
             float l2[M];
+            float lold[M];
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 part[m] = 0.0f;
                 l2[m] = lam[n][m] * lam[n][m];
+                lold[m] = lam[n][m];
             }
 #pragma unroll
             for (int k = 0; k < BPT; ++k) {
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
-                    float s = 0.0f;
+                    float w;
+                    if constexpr (kKeep) {
+                        w = wr[k][m];
+                    } else {
+                        float s = 0.0f;
 #pragma unroll
-                    for (int nn = 0; nn < N; ++nn) s = fmaf(vr[k][nn], lam[nn][m], s);
-                    const float w = rcp(s);
+                        for (int nn = 0; nn < N; ++nn) s = fmaf(vr[k][nn], lam[nn][m], s);
+                        w = rcp(s);
+                    }
                     const float r = fmaf(U[k][m], w, -1.0f);
                     const float gl = (vr[k][n] * w) * l2[m];
                     const float ek = fmaf(gl, r, lam[n][m]);
@@ -500,12 +592,13 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                 for (int m = 0; m < M; ++m) sm.redc[buf][m][wid] = part[m];
             }
             __syncthreads();
+            // every lane sums the same slots in the same order, so L stays
+            // uniform without cross-lane moves
             float c[M];
             bool good = true;
-            const float mine = lane < M ? sum_slots<NW>(sm.redc[buf][lane]) : 0.0f;
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                const float l = readlane_f(mine, m) * invTf;
+                const float l = sum_waves<NW>(sm.redc[buf][m], nw) * invTf;
                 good = good && (l > 0.0f) && (l < INFINITY);
                 lam[n][m] = l;
                 c[m] = rcp(l * static_cast<float>(M));
@@ -520,11 +613,26 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                 float s = 0.0f;
 #pragma unroll
                 for (int m = 0; m < M; ++m) s = fmaf(e[k][m], c[m], s);
-                vr[k][n] = mk[k] != 0.0f ? vr[k][n] * s : 1.0f;
+                const float vold = vr[k][n];
+                const float vnew = mk[k] != 0.0f ? vold * s : 1.0f;
+                vr[k][n] = vnew;
+                if constexpr (kKeep) {
+                    if (n + 1 < N) {
+#pragma unroll
+                        for (int m = 0; m < M; ++m) {
+                            sg[k][m] = fmaf(lam[n][m], vnew, fmaf(-lold[m], vold, sg[k][m]));
+                            wr[k][m] = rcp(sg[k][m]);
+                        }
+                    }
+                }
             }
         }
         if (status != ST_OK) break;
     }
+
+    // the likelihood wave's verdict on the last iterate
+    __syncthreads();
+    if (status == ST_OK) status = sm.flag_ll;
 
     // ---- write back the state
 #pragma unroll
