@@ -102,7 +102,9 @@ __global__ void __launch_bounds__(kResidentBins / BPT) mnmf_freq_kernel(MnmfLaun
     if (tid == 0) sm.flag = ST_OK;
     __syncthreads();
 
-    // h_jn = sum_k t_kn v_jkn for this thread's bins (1 for bins t >= T)
+    // h_jn = sum_k t_kn v_jkn for this thread's bins (1 for bins t >= T).
+    // Bins past T read frame T - 1 and drop it, so no branch splits the
+    // loads of the BPT bins and they are all in flight together.
     auto make_h = [&]() {
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
@@ -110,14 +112,12 @@ __global__ void __launch_bounds__(kResidentBins / BPT) mnmf_freq_kernel(MnmfLaun
             float s[N];
 #pragma unroll
             for (int n = 0; n < N; ++n) s[n] = 0.0f;
-            if (t < T) {
-                const float *vt = a.va + t;  // activations stored [K][N][T]
+            const float *vt = a.va + (t < T ? t : T - 1);  // activations stored [K][N][T]
 #pragma unroll 8
-                for (int kk = 0; kk < K; ++kk)
+            for (int kk = 0; kk < K; ++kk)
 #pragma unroll
-                    for (int n = 0; n < N; ++n)
-                        s[n] = fmaf(sm.t[kk * N + n], vt[static_cast<size_t>(kk * N + n) * T], s[n]);
-            }
+                for (int n = 0; n < N; ++n)
+                    s[n] = fmaf(sm.t[kk * N + n], vt[static_cast<size_t>(kk * N + n) * T], s[n]);
 #pragma unroll
             for (int n = 0; n < N; ++n) h[k][n] = t < T ? s[n] : 1.0f;
         }
@@ -300,21 +300,22 @@ __global__ void __launch_bounds__(kResidentBins / BPT) mnmf_freq_kernel(MnmfLaun
             float nd[2 * KC * N];
 #pragma unroll
             for (int e = 0; e < 2 * KC * N; ++e) nd[e] = 0.0f;
+            // bins past T have an = bn = 0 and read frame T - 1; bases past K
+            // read base K - 1 and add zero: no branch splits the loads
 #pragma unroll
             for (int k = 0; k < BPT; ++k) {
                 const int t = tid + k * nthr;
-                if (t < T) {
-                    const float *vt = a.va + t;
+                const float *vt = a.va + (t < T ? t : T - 1);
 #pragma unroll
-                    for (int c = 0; c < KC; ++c) {
-                        if (k0 + c < K) {
+                for (int c = 0; c < KC; ++c) {
+                    const bool okc = k0 + c < K;
+                    const int kc = okc ? k0 + c : K - 1;
 #pragma unroll
-                            for (int n = 0; n < N; ++n) {
-                                const float vv = vt[static_cast<size_t>((k0 + c) * N + n) * T];
-                                nd[c * N + n] = fmaf(vv, an[k][n], nd[c * N + n]);
-                                nd[KC * N + c * N + n] = fmaf(vv, bn[k][n], nd[KC * N + c * N + n]);
-                            }
-                        }
+                    for (int n = 0; n < N; ++n) {
+                        const float vl = vt[static_cast<size_t>(kc * N + n) * T];
+                        const float vv = okc ? vl : 0.0f;
+                        nd[c * N + n] = fmaf(vv, an[k][n], nd[c * N + n]);
+                        nd[KC * N + c * N + n] = fmaf(vv, bn[k][n], nd[KC * N + c * N + n]);
                     }
                 }
             }
@@ -387,68 +388,108 @@ __global__ void __launch_bounds__(kResidentBins / BPT) mnmf_freq_kernel(MnmfLaun
 // ------------------------------------------------------------------ V rule
 // Partial sums over the frequencies of chunk blockIdx.y for (j, n) =
 // divmod(index, N): part[chunk][0][k][index] = sum_i t_ikn G_ijn and
-// part[chunk][1][k][index] = sum_i t_ikn E_ijn. The chunk's t is staged in
-// LDS; G and E loads are coalesced over the index.
-__global__ void __launch_bounds__(64) mnmf_v_partial_kernel(const float *G, const float *E, const float *tp,
-                                                            float *part, int F, int T, int N, int K,
-                                                            int fchunk) {
-    __shared__ float ts[kMnmfFChunk * kMnmfKMax * kMnmfNMax];
+// part[chunk][1][k][index] = sum_i t_ikn E_ijn, each summed over the chunk's
+// frequencies in ascending order. The chunk's t is staged in LDS as
+// [i][n][k] (zero past the last frequency and past K), so four consecutive
+// bases are one 16-byte LDS read; G and E loads are coalesced over the index
+// and all in flight before the first FMA.
+constexpr int kVThreads = 256;
+__global__ void __launch_bounds__(kVThreads) mnmf_v_partial_kernel(const float *G, const float *E, const float *tp,
+                                                                   float *part, int F, int T, int N, int K,
+                                                                   int fchunk) {
+    __shared__ __align__(16) float ts[kMnmfFChunk][kMnmfNMax][kMnmfKMax];
     const int c = blockIdx.y;
     const int i0 = c * fchunk;
     const int ni = min(F, i0 + fchunk) - i0;
-    // t of the chunk, [ii][k][n]; zero past the last frequency
-    for (int q = threadIdx.x; q < kMnmfFChunk * K * N; q += blockDim.x)
-        ts[q] = q < ni * K * N ? tp[static_cast<size_t>(i0) * K * N + q] : 0.0f;
-    __syncthreads();
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const int TN = T * N;
-    if (idx >= TN) return;
-    const int n = idx % N;
-    const float *Gp = G + static_cast<size_t>(i0) * TN + idx;
-    const float *Ep = E + static_cast<size_t>(i0) * TN + idx;
-    // every load of the chunk in flight before the first FMA
+    const bool live = idx < TN;
+    // the chunk's G and E first, so their latency overlaps the staging of t
     float gs[kMnmfFChunk], es[kMnmfFChunk];
-#pragma unroll
-    for (int ii = 0; ii < kMnmfFChunk; ++ii) {
-        gs[ii] = ii < ni ? Gp[static_cast<size_t>(ii) * TN] : 0.0f;
-        es[ii] = ii < ni ? Ep[static_cast<size_t>(ii) * TN] : 0.0f;
-    }
-    float *pn = part + static_cast<size_t>(c) * 2 * K * TN + idx;
-    for (int k = 0; k < K; ++k) {
-        float num = 0.0f, den = 0.0f;
-        const float *tk = ts + k * N + n;
+    {
+        const float *Gp = G + static_cast<size_t>(i0) * TN + idx;
+        const float *Ep = E + static_cast<size_t>(i0) * TN + idx;
 #pragma unroll
         for (int ii = 0; ii < kMnmfFChunk; ++ii) {
-            const float t = tk[ii * K * N];
-            num = fmaf(t, gs[ii], num);
-            den = fmaf(t, es[ii], den);
+            gs[ii] = (live && ii < ni) ? Gp[static_cast<size_t>(ii) * TN] : 0.0f;
+            es[ii] = (live && ii < ni) ? Ep[static_cast<size_t>(ii) * TN] : 0.0f;
         }
-        pn[static_cast<size_t>(k) * TN] = num;
-        pn[static_cast<size_t>(K + k) * TN] = den;
+    }
+    // every slot of the stage, its loads all issued before the first store
+    constexpr int kStage = kMnmfFChunk * kMnmfNMax * kMnmfKMax / kVThreads;
+    static_assert(kStage * kVThreads == kMnmfFChunk * kMnmfNMax * kMnmfKMax, "stage tiling");
+    float tv[kStage];
+#pragma unroll
+    for (int r = 0; r < kStage; ++r) {
+        const int q = threadIdx.x + r * kVThreads;
+        const int ii = q / (kMnmfNMax * kMnmfKMax);
+        const int n = (q / kMnmfKMax) % kMnmfNMax;
+        const int k = q % kMnmfKMax;
+        tv[r] = (ii < ni && n < N && k < K) ? tp[(static_cast<size_t>(i0 + ii) * K + k) * N + n] : 0.0f;
+    }
+#pragma unroll
+    for (int r = 0; r < kStage; ++r) (&ts[0][0][0])[threadIdx.x + r * kVThreads] = tv[r];
+    __syncthreads();
+    if (!live) return;
+    const int n = idx % N;
+    float *pn = part + static_cast<size_t>(c) * 2 * K * TN + idx;
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        float num[4] = {0.f, 0.f, 0.f, 0.f}, den[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ii = 0; ii < kMnmfFChunk; ++ii) {
+            const float4 t4 = *reinterpret_cast<const float4 *>(&ts[ii][n][k0]);
+            num[0] = fmaf(t4.x, gs[ii], num[0]);
+            num[1] = fmaf(t4.y, gs[ii], num[1]);
+            num[2] = fmaf(t4.z, gs[ii], num[2]);
+            num[3] = fmaf(t4.w, gs[ii], num[3]);
+            den[0] = fmaf(t4.x, es[ii], den[0]);
+            den[1] = fmaf(t4.y, es[ii], den[1]);
+            den[2] = fmaf(t4.z, es[ii], den[2]);
+            den[3] = fmaf(t4.w, es[ii], den[3]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (k0 + q < K) {
+                pn[static_cast<size_t>(k0 + q) * TN] = num[q];
+                pn[static_cast<size_t>(K + k0 + q) * TN] = den[q];
+            }
+        }
     }
 }
 
 // v_jkn <- v_jkn sqrt(num / den), the chunk partials summed in chunk order;
-// one thread per (k, n, j), activations stored [K][N][T].
+// one thread per (k, index) with index = j N + n, so the partial loads are
+// coalesced; activations stored [K][N][T].
 __global__ void __launch_bounds__(256) mnmf_v_update_kernel(const float *part, float *va, int nchunk, int T,
                                                             int N, int K, int *flag) {
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     const int TN = T * N;
     if (gid >= TN * K) return;
     const int k = gid / TN;
-    const int rem = gid - k * TN;
-    const int n = rem / T, j = rem - n * T;
-    const int idx = j * N + n;
+    const int idx = gid - k * TN;
+    const int j = idx / N, n = idx - j * N;
     float num = 0.0f, den = 0.0f;
     const float *pc = part + static_cast<size_t>(k) * TN + idx;
     const size_t cs = static_cast<size_t>(2) * K * TN;
     const size_t ds = static_cast<size_t>(K) * TN;
-#pragma unroll 8
-    for (int c = 0; c < nchunk; ++c) {
-        num += pc[c * cs];
-        den += pc[c * cs + ds];
+    // up to 32 chunks' loads in flight at once; the zeros past the last
+    // chunk leave the sums unchanged
+    constexpr int kCB = 32;
+    for (int c0 = 0; c0 < nchunk; c0 += kCB) {
+        float a[kCB], b[kCB];
+#pragma unroll
+        for (int q = 0; q < kCB; ++q) {
+            const bool ok = c0 + q < nchunk;
+            a[q] = ok ? pc[(c0 + q) * cs] : 0.0f;
+            b[q] = ok ? pc[(c0 + q) * cs + ds] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < kCB; ++q) {
+            num += a[q];
+            den += b[q];
+        }
     }
-    float *v = va + static_cast<size_t>(gid);  // (k N + n) T + j
+    float *v = va + static_cast<size_t>(k * N + n) * T + j;
     const float nv = *v * sqrtf(num / den);
     if (!(nv > 0.0f) || !(nv < INFINITY)) *flag = 1;
     *v = nv;
@@ -526,8 +567,8 @@ hipError_t launch_mnmf_v(const float *G, const float *E, const float *tp, float 
     const int nchunk = (F + fchunk - 1) / fchunk;
     const int TN = T * N;
     if (fchunk > kMnmfFChunk || N > kMnmfNMax) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(mnmf_v_partial_kernel, dim3((TN + 63) / 64, nchunk), dim3(64), 0, s, G, E, tp, part, F, T,
-                       N, K, fchunk);
+    hipLaunchKernelGGL(mnmf_v_partial_kernel, dim3((TN + kVThreads - 1) / kVThreads, nchunk), dim3(kVThreads), 0, s,
+                       G, E, tp, part, F, T, N, K, fchunk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(mnmf_v_update_kernel, dim3((TN * K + 255) / 256), dim3(256), 0, s, part, va, nchunk, T, N,
