@@ -312,6 +312,22 @@ def bench_batch(args):
         c.close()
     updates = sum(s["F"] * s["T"] * s["N"] for s in specs) * iters
     bins = sum(s["F"] * s["T"] for s in specs)
+    flops = sum(s["F"] * s["T"] * em_flops_per_bin(s["M"], s["N"]) for s in specs) * iters
+    oracle_sample = None
+    if not args.no_cpu:
+        # the oracle on a bounded sample: the first 16 mixtures, 128 frequencies each, 10 iterations
+        import oracle
+        from paper_2101_08563_amd import synth as _synth
+        t_cpu, upd_cpu = 0.0, 0
+        for i, s in enumerate(specs[:16]):
+            xh = xs[i][:128].cpu().numpy()
+            P0, l0, v0 = _synth.init_params(xh, s["N"], config_id=2, mixture_id=i)
+            t2 = time.perf_counter()
+            oracle.fit(xh, P0, l0, v0, 10)
+            t_cpu += time.perf_counter() - t2
+            upd_cpu += xh.shape[0] * xh.shape[1] * s["N"] * 10
+        oracle_sample = {"value": upd_cpu / t_cpu, "unit": "updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+                         "sample": "16 of 256 mixtures, 128 of 513 frequencies each, 10 iterations, %.2f s" % t_cpu}
     out = {"metric": "EM TF-bin*source updates/s", "value": updates / (t_batch * 1e-3), "unit": "updates/s",
            "n_gpus": 1, "steps": max(2, args.steps // 5), "warmup": 1, "ms_per_step": t_batch,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -321,7 +337,13 @@ def bench_batch(args):
                                                                else "one launch per (M, N, T-bucket) class"),
                       "iters": iters, "tf_bins": bins, "autotune": tune,
                       "sequential_ms": t_seq, "speedup_vs_sequential": t_seq / t_batch,
-                      "sequential_updates_per_s": updates / (t_seq * 1e-3)}}
+                      "sequential_updates_per_s": updates / (t_seq * 1e-3)},
+           "roofline": {"kernel": "em_persistent_kernel" if tune["persistent"] else "em_kernel class launches",
+                        "bound": "alu",
+                        "achieved": flops / (t_batch * 1e-3) / 1e12, "peak": FP32_FMA_PEAK / 1e12,
+                        "unit": "TFLOP/s", "frac": flops / (t_batch * 1e-3) / FP32_FMA_PEAK, "traffic": None}}
+    if oracle_sample:
+        out["cpu_baseline"] = oracle_sample
     print(json.dumps(out))
 
 
