@@ -497,11 +497,13 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                     }
                 }
             }
+            constexpr int NG = (2 * N * M + 3) / 4;
+            float tot[NG];
+            wave_sums_rows<2 * N * M>(nd, tot);
+            if ((lane & 15) == 0) {
 #pragma unroll
-            for (int i = 0; i < 2 * N * M; ++i) nd[i] = wave_sum_last(nd[i]);
-            if (lane == 63) {
-#pragma unroll
-                for (int i = 0; i < 2 * N * M; ++i) sm.redc[buf][i][wid] = nd[i];
+                for (int g = 0; g < NG; ++g)
+                    if (4 * g + (lane >> 4) < 2 * N * M) sm.redc[buf][4 * g + (lane >> 4)][wid] = tot[g];
             }
             __syncthreads();
             const float mine = lane < 2 * N * M ? sum_waves<NW>(sm.redc[buf][lane], nw) : 0.0f;
@@ -585,12 +587,9 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                     part[m] = fmaf(mk[k], ek, part[m]);
                 }
             }
-#pragma unroll
-            for (int m = 0; m < M; ++m) part[m] = wave_sum_last(part[m]);
-            if (lane == 63) {
-#pragma unroll
-                for (int m = 0; m < M; ++m) sm.redc[buf][m][wid] = part[m];
-            }
+            float tot[1];
+            wave_sums_rows<M>(part, tot);
+            if ((lane & 15) == 0 && (lane >> 4) < M) sm.redc[buf][lane >> 4][wid] = tot[0];
             __syncthreads();
             // every lane sums the same slots in the same order, so L stays
             // uniform without cross-lane moves
