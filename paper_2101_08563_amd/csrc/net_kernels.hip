@@ -102,12 +102,25 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(const float *X, int Cin, 
     const int tbeg = blockIdx.x * kChunk;
     const int tend = min(T, tbeg + kChunk);
     const bool vec = (Cin % 4) == 0;
+    // X tiles are staged through registers with every load of a tile issued
+    // at once, before the first LDS store
+    constexpr int kStage = (kMaxC * XW + 255) / 256;
     for (int t0 = tbeg; t0 < tend; t0 += kTile) {
         __syncthreads();
-        for (int i = tid; i < Cin * XW; i += 256) {
-            const int ci = i / XW, tt = i % XW;
-            const int t = t0 + tt - R;
-            xs[tt][ci] = f2bf((t >= 0 && t < T) ? Xs[static_cast<size_t>(ci) * T + t] : 0.0f);
+        {
+            float sv[kStage];
+#pragma unroll
+            for (int r = 0; r < kStage; ++r) {
+                const int i = tid + 256 * r;
+                const int ci = i / XW, tt = i % XW;
+                const int t = t0 + tt - R;
+                sv[r] = (i < Cin * XW && t >= 0 && t < T) ? Xs[static_cast<size_t>(ci) * T + t] : 0.0f;
+            }
+#pragma unroll
+            for (int r = 0; r < kStage; ++r) {
+                const int i = tid + 256 * r;
+                if (i < Cin * XW) xs[i % XW][i / XW] = f2bf(sv[r]);
+            }
         }
         __syncthreads();
         if (!active) continue;
