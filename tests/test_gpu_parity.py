@@ -229,7 +229,8 @@ def test_zero_frequency_is_reported_singular():
     assert rel(v[keep], vo) < 1e-4
 
 
-@pytest.mark.parametrize("M,N,T,F", [(2, 3, 1000, 64), (3, 4, 700, 9), (4, 6, 400, 7), (2, 2, 77, 5)])
+@pytest.mark.parametrize("M,N,T,F", [(2, 3, 1000, 64), (3, 4, 700, 9), (4, 6, 400, 7), (2, 2, 77, 5),
+                                     (3, 3, 500, 6), (3, 5, 300, 5)])
 def test_ip_mm_algorithm2_parity(M, N, T, F):
     """Algorithm 2 (IP+MM) against the oracle's IP+MM."""
     x, P0, lam0, v0 = make_case(F, T, M, N, config_id=90 + M, mixture_id=N)
