@@ -41,17 +41,18 @@ constexpr double kLnPi = 1.1447298858494002;  // ln(pi)
 // per wave of the largest workgroup it allows, at least 4.
 constexpr int wave_slots(int bpt) { return kResidentBins / bpt / 64 < 4 ? 4 : kResidentBins / bpt / 64; }
 
-// LDS of one workgroup. Phase A (the M^3 parameters of the Q_m and the
-// likelihood terms) leaves one partial per 16-lane row, four per wave, in
-// redq / red_d; each L reduction of phase C (M values, or the 2NM sums of the
-// multiplicative rule) one partial per wave in redc, double buffered so that
-// one barrier per reduction suffices. Slots of waves that do not exist stay
-// zero. RQ >= M^3, RC >= 2NM values; NWS wave slots.
+// LDS of one workgroup. Phase A leaves one partial per wave of each of the
+// M^3 parameters of the Q_m in redq and one partial per 16-lane row (four per
+// wave) of the likelihood terms in red_d; each L reduction of phase C (M
+// values, or the 2NM sums of the multiplicative rule) one partial per wave in
+// redc, double buffered so that one barrier per reduction suffices. Slots of
+// waves that do not exist stay zero. RQ >= M^3, RC >= 2NM values; NWS wave
+// slots.
 template <int RQ, int RC, int NWS>
 struct EmSmem {
     static constexpr int kRowSlots = 4 * NWS;
     static constexpr int kWaveSlots = NWS;
-    alignas(16) float redq[RQ][4 * NWS];
+    alignas(16) float redq[RQ][NWS];
     alignas(16) double red_d[4 * NWS];
     alignas(16) float redc[2][RC][NWS];
     double qtot[RQ];
@@ -369,19 +370,20 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                     for (int e = 0; e < M * M; ++e) q[m * M * M + e] = fmaf(w[m], z[e], q[m * M * M + e]);
             }
         }
-        // row partials of Q and of the LL terms to LDS
+        // wave partials of Q (four values per reduction, value 4g + r in row
+        // r) and row partials of the LL terms to LDS
         if (!last) {
+            constexpr int NGQ = (NQ + 3) / 4;
+            float tq[NGQ];
+            wave_sums_rows<NQ>(q, tq);
+            if ((lane & 15) == 0) {
 #pragma unroll
-            for (int i = 0; i < NQ; ++i) q[i] = row_sum(q[i]);
+                for (int g = 0; g < NGQ; ++g)
+                    if (4 * g + (lane >> 4) < NQ) sm.redq[4 * g + (lane >> 4)][wid] = tq[g];
+            }
         }
         double llp = row_sum(static_cast<double>(lg2) * static_cast<double>(kLn2f) + static_cast<double>(uw));
-        if (row_lead) {
-            if (!last) {
-#pragma unroll
-                for (int i = 0; i < NQ; ++i) sm.redq[i][row_slot] = q[i];
-            }
-            sm.red_d[row_slot] = llp;
-        }
+        if (row_lead) sm.red_d[row_slot] = llp;
         __syncthreads();
         if (wid == llw && iter > 0) {
             // eq:negll for the previous iterate, beside the IP on wave 0
@@ -398,12 +400,12 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                 // lane i sums value i over the row slots, then every lane
                 // reads all eight sums from registers
                 double qs[8];
-                const float mine = lane < 8 ? sum_rows<NR>(sm.redq[lane], nw) : 0.0f;
+                const float mine = lane < 8 ? sum_waves<NW>(sm.redq[lane], nw) : 0.0f;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) qs[i] = static_cast<double>(readlane_f(mine, i)) * invT;
                 status = ip_sweep_reg2(sm, qs, ldet);
             } else {
-                if (lane < NQ) sm.qtot[lane] = static_cast<double>(sum_rows<NR>(sm.redq[lane], nw)) * invT;
+                if (lane < NQ) sm.qtot[lane] = static_cast<double>(sum_waves<NW>(sm.redq[lane], nw)) * invT;
                 __threadfence_block();
                 __builtin_amdgcn_wave_barrier();
                 // lane-parallel IP sweep in double precision
