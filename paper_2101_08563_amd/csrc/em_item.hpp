@@ -175,11 +175,14 @@ __device__ __forceinline__ float sum_waves(const float *p, int nw) {
 // one reciprocal square root per column and no division. The system is
 // taken as singular when |det(P^H Q)|^2 = |d|^2 det(Q)^2 falls below
 // tol^2 (|P|_F^2 |Q|_F^2)^2, the fourth power of a bound on its largest entry.
-// q: the 8 reduced Hermitian parameters (Q_1 then Q_2), already / T.
+// q: the 8 Hermitian parameters (Q_1 then Q_2) of T Q_m, the sums before
+// the division by T; qscale = sqrt(T). Scaling Q by T scales u and s by T and
+// det Q by T^2, so w of the scaled sums is w / sqrt(T), and the pivot test
+// is scale free: one multiplication per column replaces eight scalings.
 // The checks are folded into one status without branches; nothing is
 // stored unless both columns pass.
 template <class Smem>
-__device__ __forceinline__ int ip_sweep_reg2(Smem &sm, const double (&q)[8], double &ldet) {
+__device__ __forceinline__ int ip_sweep_reg2(Smem &sm, const double (&q)[8], double qscale, double &ldet) {
     cd P00 = ld(sm.Pd[0]), P01 = ld(sm.Pd[1]), P10 = ld(sm.Pd[2]), P11 = ld(sm.Pd[3]);
     int stat = ST_OK;
 #pragma unroll
@@ -200,7 +203,7 @@ __device__ __forceinline__ int ip_sweep_reg2(Smem &sm, const double (&q)[8], dou
         const double t = sb * dq * d2;
         const bool piv = (d2 * dq * dq >= kPivotTol * kPivotTol * (np * nq) * (np * nq)) && (t > 0.0) && (t < INFINITY);
         stat = stat != ST_OK ? stat : (!fin ? ST_NONFINITE : (!piv ? ST_SINGULAR : ST_OK));
-        const double r = rsqrt_d(t);
+        const double r = rsqrt_d(t) * qscale;
         const cd w0 = r * (u0 * d), w1 = r * (u1 * d);
         if (m == 0) {
             P00 = w0;
@@ -245,6 +248,7 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
     const int T = it.T;
     const float invTf = 1.0f / static_cast<float>(T);
     const double invT = 1.0 / static_cast<double>(T);
+    const double sqrtT = sqrt(static_cast<double>(T));
 
     // ---- load the frequency's state. Bins t >= T hold x = 0 and h = 1: they
     // add nothing to Q or U, and mk = 0 drops them from the other sums.
@@ -402,8 +406,8 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                 double qs[8];
                 const float mine = lane < 8 ? sum_waves<NW>(sm.redq[lane], nw) : 0.0f;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) qs[i] = static_cast<double>(readlane_f(mine, i)) * invT;
-                status = ip_sweep_reg2(sm, qs, ldet);
+                for (int i = 0; i < 8; ++i) qs[i] = static_cast<double>(readlane_f(mine, i));
+                status = ip_sweep_reg2(sm, qs, sqrtT, ldet);
             } else {
                 if (lane < NQ) sm.qtot[lane] = static_cast<double>(sum_waves<NW>(sm.redq[lane], nw)) * invT;
                 __threadfence_block();

@@ -218,8 +218,8 @@ __global__ void __launch_bounds__(kResidentBins / BPT) mnmf_freq_kernel(MnmfLaun
             double qs[8];
             const float mine = lane < 8 ? sum_slots<NR>(sm.redq[lane]) : 0.0f;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) qs[e] = static_cast<double>(readlane_f(mine, e)) * invT;
-            st = ip_sweep_reg2(sm, qs, ldet);
+            for (int e = 0; e < 8; ++e) qs[e] = static_cast<double>(readlane_f(mine, e));
+            st = ip_sweep_reg2(sm, qs, sqrt(static_cast<double>(T)), ldet);
         } else {
             if (lane < NQ) sm.qtot[lane] = static_cast<double>(sum_slots<NR>(sm.redq[lane])) * invT;
             __threadfence_block();
