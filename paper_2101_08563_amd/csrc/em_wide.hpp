@@ -265,12 +265,19 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, Wid
                     phis[(k * M + m) * 64 + lane] = ph;
                     pm = fmaf(ph, rv[k], pm);
                 }
-                part[m] = wave_sum(pm);
+                part[m] = pm;
                 __builtin_amdgcn_sched_barrier(0);
             }
-            if (lane == 0) {
+            {
+                // wave sums four values at a time, value 4g + r in row r
+                constexpr int NG = (M + 3) / 4;
+                float tot[NG];
+                wave_sums_rows<M>(part, tot);
+                if ((lane & 15) == 0) {
 #pragma unroll
-                for (int m = 0; m < M; ++m) sm.red[buf][m][wid] = part[m];
+                    for (int g = 0; g < NG; ++g)
+                        if (4 * g + (lane >> 4) < M) sm.red[buf][4 * g + (lane >> 4)][wid] = tot[g];
+                }
             }
             __syncthreads();
             float s16 = 0.0f;
