@@ -349,6 +349,29 @@ int fastfca_net_mean_t(const float *H, int SC, int T, float *pooled, void *strea
 /* dH[i][t] += dpooled[i] / T. */
 int fastfca_net_mean_t_bwd(const float *dpooled, int SC, int T, float *dH, void *stream);
 
+/*
+ * fastfca_net_forward_fused -- inference forward of the whole network in one
+ * launch: the kernel-5 input layer, L residual kernel-5 layers and the 1x1
+ * head, for tiles of 64 frames with the activations in LDS (the same BF16
+ * operands and FP32 accumulation as fastfca_net_conv_fwd; the head in FP32).
+ *   feat    device [S][M][T] float32 features, M <= 4
+ *   Wb, b   HOST arrays of L + 1 device pointers: packed BF16 weights of the
+ *           kernel-5 layers (layer 0 [C][Kp0], Kp0 a multiple of 16 >= 5 M;
+ *           layers 1..L [C][5 C]) and their FP32 biases [C]
+ *   Wv, bv  device FP32 head weights [N][ldv] (entry c of row n, ldv >= C)
+ *           and biases [N], N <= 8
+ *   lv      device [S][N][T] output (log v before the positivity map)
+ *   part    device scratch, S * ceil(T / 64) * C floats
+ *   pooled  device [S][C] output, the mean over t of the last layer
+ * C a multiple of 16 up to 64, L <= 8. E_ARG on other shapes or NULL
+ * pointers. Asynchronous on hip_stream. For inference only: no activation is
+ * kept for the backward pass.
+ */
+int fastfca_net_forward_fused(const float *feat, int S, int M, int T, int C, int L, int N,
+                              const uint16_t *const *Wb, const float *const *b, int Kp0,
+                              const float *Wv, int ldv, const float *bv, float *lv, float *part,
+                              float *pooled, void *stream);
+
 /* out[s][j] = bl[j] + sum_c Wl[j][c] in[s][c]. */
 int fastfca_net_linear_fwd(const float *in, int S, int C, const float *Wl, const float *bl, int J,
                            float *out, void *stream);

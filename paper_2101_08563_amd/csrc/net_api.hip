@@ -17,6 +17,9 @@ hipError_t net_conv_bwdw(const float *G, int S, int Cout, const float *X, int Ci
                          float *dW, float *db, hipStream_t s);
 hipError_t net_relu_grad(const float *G, const float *Pre, float *out, size_t n, hipStream_t s);
 hipError_t net_mean_t(const float *H, int SC, int T, float *pooled, hipStream_t s);
+hipError_t net_forward_fused(const float *feat, int S, int M, int T, int C, int L, int N,
+                             const uint16_t *const *Wb, const float *const *b, int Kp0, const float *Wv, int ldv,
+                             const float *bv, float *lv, float *part, float *pooled, hipStream_t s);
 hipError_t net_mean_t_bwd(const float *dpooled, int SC, int T, float *dH, hipStream_t s);
 hipError_t net_linear_fwd(const float *in, int S, int C, const float *Wl, const float *bl, int J, float *out,
                           hipStream_t s);
@@ -90,6 +93,14 @@ int fastfca_net_mean_t(const float *H, int SC, int T, float *pooled, void *strea
 int fastfca_net_mean_t_bwd(const float *dpooled, int SC, int T, float *dH, void *stream) {
     if (!dpooled || !dH || SC < 1 || T < 1) return bad("mean_t_bwd");
     return fin(net_mean_t_bwd(dpooled, SC, T, dH, st(stream)), "mean_t_bwd");
+}
+
+int fastfca_net_forward_fused(const float *feat, int S, int M, int T, int C, int L, int N,
+                              const uint16_t *const *Wb, const float *const *b, int Kp0, const float *Wv, int ldv,
+                              const float *bv, float *lv, float *part, float *pooled, void *stream) {
+    if (!feat || !Wb || !b || !Wv || !bv || !lv || !part || !pooled) return bad("forward_fused");
+    return fin(net_forward_fused(feat, S, M, T, C, L, N, Wb, b, Kp0, Wv, ldv, bv, lv, part, pooled, st(stream)),
+               "forward_fused");
 }
 
 int fastfca_net_linear_fwd(const float *in, int S, int C, const float *Wl, const float *bl, int J, float *out,

@@ -182,6 +182,191 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(const float *X, int Cin, 
     }
 }
 
+// ------------------------------------------------------------------ fused inference
+// The whole forward pass for one sequence and one tile of kFT output frames
+// in one workgroup, with the activations in LDS: the kernel-5 input layer,
+// the L residual layers and the 1x1 head. Each kernel-5 layer narrows the
+// valid frames by 2 on each side, so the tile is computed over kFT + 4 (L + 1)
+// input frames (a 2 (L + 1)-frame halo each side) and rows whose frame lies
+// outside [0, T) are held at zero, which is the "same" zero padding of the
+// layer-by-layer convolutions. The convolutions use the same BF16 fragments,
+// the same k order and the same MFMA sequence as conv_fwd_kernel; the
+// residual stream stays FP32 (hf), and the BF16 copy that feeds the MFMAs
+// alternates between two buffers, so a wave stores each 16-frame block of a
+// layer as soon as it is done, with one barrier per layer. The head (N outputs) and the per-tile sums of h_L over frames are
+// plain FP32; the tile sums are combined in order by pool_tiles_kernel.
+constexpr int kFT = 64;                                // output frames per tile
+constexpr int kFMaxL = 8;                              // residual layers
+constexpr int kFMaxN = 8;                              // head outputs
+constexpr int kFRows = kFT + 4 * (kFMaxL + 1) + 16;    // input rows + overrun of the last 16-row block
+
+struct FusedNetArgs {
+    const float *feat;  // [S][M][T]
+    float *lv;          // [S][N][T]
+    float *part;        // [S][ntiles][C]
+    const uint16_t *W[kFMaxL + 1];
+    const float *b[kFMaxL + 1];
+    const float *Wv;    // [N][ldv], FP32 head weights
+    const float *bv;    // [N]
+    int S, M, T, C, L, N, Kp0, ldv, ntiles;
+};
+
+template <int C>
+__global__ void __launch_bounds__(256) net_fused_fwd_kernel(FusedNetArgs a) {
+    __shared__ __align__(16) float hf[kFRows][kMaxC + 1];
+    __shared__ __align__(16) uint16_t hb[2][kFRows][kMaxC + 4];  // layer input / output, alternating
+    __shared__ __align__(16) uint16_t fb[kFRows][4];
+    __shared__ float wvs[kFMaxN][kMaxC];
+    __shared__ float bs[kFMaxL + 1][kMaxC];
+    const int s = blockIdx.y, tile = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lq = lane >> 4;
+    const int L = a.L, T = a.T, M = a.M;
+    const int H = 2 * (L + 1);
+    const int W0 = kFT + 2 * H;
+    const int t0 = tile * kFT;
+    const int fr0 = t0 - H;  // frame of row 0
+    for (int i = tid; i < 2 * kFRows * (kMaxC + 4) / 2; i += 256) reinterpret_cast<uint32_t *>(&hb[0][0][0])[i] = 0u;
+    for (int i = tid; i < kFRows * 2; i += 256) reinterpret_cast<uint32_t *>(&fb[0][0])[i] = 0u;
+    for (int i = tid; i < a.N * C; i += 256) wvs[i / C][i % C] = a.Wv[static_cast<size_t>(i / C) * a.ldv + i % C];
+    for (int i = tid; i < (L + 1) * C; i += 256) bs[i / C][i % C] = a.b[i / C][i % C];
+    __syncthreads();
+    for (int i = tid; i < M * W0; i += 256) {
+        const int ci = i / W0, r = i % W0;
+        const int t = fr0 + r;
+        fb[r][ci] = f2bf((t >= 0 && t < T) ? a.feat[(static_cast<size_t>(s) * M + ci) * T + t] : 0.0f);
+    }
+    __syncthreads();
+
+    const bool act = 16 * w < C;  // wave w owns channels 16 w .. 16 w + 15
+    // output rows [lo, hi) of a layer: activation, residual, zero padding
+    // (res: the residual values of the lane's four outputs, zero for layer 0)
+    auto store = [&](int l, int j, int lo, int hi, const f32x4 &c, const f32x4 &res,
+                     uint16_t (*out)[kMaxC + 4]) {
+        const int r = lo + 16 * j + li;
+        if (r >= hi) return;
+        const int t = fr0 + r;
+        const bool in = t >= 0 && t < T;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int co = 16 * w + 4 * lq + v;
+            const float val = in ? res[v] + fmaxf(c[v] + bs[l][co], 0.0f) : 0.0f;
+            hf[r][co] = val;
+            out[r][co] = f2bf(val);
+        }
+    };
+
+    // this wave's 16 weight rows of a residual layer, every fragment load in
+    // flight at once; the next layer's are loaded while this one computes
+    constexpr int nkb = 5 * C / 16;
+    auto load_frags = [&](int l, bf16x4 (&af)[nkb]) {
+        const uint16_t *Wl = a.W[l] + static_cast<size_t>(16 * w + li) * (5 * C) + 4 * lq;
+#pragma unroll
+        for (int kb = 0; kb < nkb; ++kb) af[kb] = *reinterpret_cast<const bf16x4 *>(Wl + 16 * kb);
+    };
+    bf16x4 afn[nkb];
+    if (act && L >= 1) load_frags(1, afn);
+
+    // layer 0: M input channels, one or two 16-wide k blocks, gathered from fb
+    if (act) {
+        const int Kp = a.Kp0;
+        const uint16_t *Wl = a.W[0] + static_cast<size_t>(16 * w + li) * Kp + 4 * lq;
+        const int lo = 2, hi = W0 - 2;
+        const int nblk = (hi - lo + 15) / 16;
+        for (int j = 0; j < nblk; ++j) {
+            f32x4 c = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int kb = 0; kb < Kp / 16; ++kb) {
+                const bf16x4 af = *reinterpret_cast<const bf16x4 *>(Wl + 16 * kb);
+                const int rb = lo + 16 * j + li - 2;
+                bf16x4 bq;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int kk = 16 * kb + 4 * lq + q;
+                    const int k = kk / M, ci = kk - k * M;
+                    bq[q] = kk < 5 * M ? static_cast<short>(fb[rb + k][ci]) : 0;
+                }
+                c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bq, c, 0, 0, 0);
+            }
+            store(0, j, lo, hi, c, f32x4{0.f, 0.f, 0.f, 0.f}, hb[0]);
+        }
+    }
+    __syncthreads();
+
+    // residual layers: input hb[(l + 1) & 1], output hb[l & 1]
+    for (int l = 1; l <= L; ++l) {
+        uint16_t (*in)[kMaxC + 4] = hb[(l + 1) & 1];
+        uint16_t (*out)[kMaxC + 4] = hb[l & 1];
+        const int lo = 2 * (l + 1), hi = W0 - 2 * (l + 1);
+        const int nblk = (hi - lo + 15) / 16;
+        if (act) {
+            bf16x4 af[nkb];
+#pragma unroll
+            for (int kb = 0; kb < nkb; ++kb) af[kb] = afn[kb];
+            if (l < L) load_frags(l + 1, afn);
+#pragma unroll 1
+            for (int j = 0; j < nblk; ++j) {
+                const int rb = lo + 16 * j + li - 2;  // input row of tap 0
+                // every B fragment of the block read before the first MFMA
+                bf16x4 bq[nkb];
+#pragma unroll
+                for (int kb = 0; kb < nkb; ++kb) {
+                    const int kk0 = 16 * kb + 4 * lq;
+                    const int k = kk0 / C, ci = kk0 - k * C;
+                    bq[kb] = *reinterpret_cast<const bf16x4 *>(&in[rb + k][ci]);
+                }
+                // the residual of the lane's outputs (rows past the layer read a
+                // row inside the buffer and are not stored)
+                f32x4 res;
+                {
+                    const int r = min(lo + 16 * j + li, kFRows - 1);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) res[v] = hf[r][16 * w + 4 * lq + v];
+                }
+                __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the MFMA chains
+                // two accumulators (even and odd k blocks) so that consecutive
+                // MFMAs do not wait on each other
+                f32x4 c0 = f32x4{0.f, 0.f, 0.f, 0.f}, c1 = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kb = 0; kb + 1 < nkb; kb += 2) {
+                    c0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[kb], bq[kb], c0, 0, 0, 0);
+                    c1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[kb + 1], bq[kb + 1], c1, 0, 0, 0);
+                }
+                if constexpr (nkb % 2) c0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[nkb - 1], bq[nkb - 1], c0, 0, 0, 0);
+                const f32x4 c = c0 + c1;
+                store(l, j, lo, hi, c, res, out);
+            }
+        }
+        __syncthreads();
+    }
+    // head: log v[n][t] = bv[n] + sum_c Wv[n][c] h_L[t][c]
+    for (int q = tid; q < a.N * kFT; q += 256) {
+        const int n = q / kFT, i = q - n * kFT;
+        const int t = t0 + i;
+        if (t < T) {
+            float y = a.bv[n];
+            for (int c = 0; c < C; ++c) y = fmaf(wvs[n][c], hf[H + i][c], y);
+            a.lv[(static_cast<size_t>(s) * a.N + n) * T + t] = y;
+        }
+    }
+    // this tile's sum of h_L over its frames, per channel
+    for (int c = tid; c < C; c += 256) {
+        float sum = 0.0f;
+        for (int i = 0; i < kFT && t0 + i < T; ++i) sum += hf[H + i][c];
+        a.part[(static_cast<size_t>(s) * a.ntiles + tile) * C + c] = sum;
+    }
+}
+
+// pooled[s][c] = (1/T) sum over tiles in order of part[s][tile][c]
+__global__ void pool_tiles_kernel(const float *part, int S, int ntiles, int C, int T, float *pooled) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S * C) return;
+    const int s = i / C, c = i - s * C;
+    float sum = 0.0f;
+    for (int k = 0; k < ntiles; ++k) sum += part[(static_cast<size_t>(s) * ntiles + k) * C + c];
+    pooled[i] = sum / static_cast<float>(T);
+}
+
 // ------------------------------------------------------------------ weight gradient
 // dW[co][ci*KS + k] += sum_t G[s][co][t] X[s][ci][t + k - R];  db[co] += sum_t G[s][co][t].
 // Computed as the GEMM over kk = k * Cin + ci. Grid (ceil(T / kChunk), S): a
@@ -669,6 +854,46 @@ hipError_t net_conv_fwd(const float *X, int S, int Cin, int T, const uint16_t *W
                            Res, Pre);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t net_forward_fused(const float *feat, int S, int M, int T, int C, int L, int N,
+                             const uint16_t *const *Wb, const float *const *b, int Kp0, const float *Wv, int ldv,
+                             const float *bv, float *lv, float *part, float *pooled, hipStream_t s) {
+    if (S < 1 || T < 1 || M < 1 || M > 4 || C < 16 || C > kMaxC || C % 16 || L < 0 || L > kFMaxL || N < 1 ||
+        N > kFMaxN || Kp0 % 16 || Kp0 < 5 * M || Kp0 > kMaxKp || 5 * C > kMaxKp || ldv < C)
+        return hipErrorInvalidValue;
+    FusedNetArgs a;
+    a.feat = feat;
+    a.lv = lv;
+    a.part = part;
+    for (int l = 0; l <= kFMaxL; ++l) {
+        a.W[l] = l <= L ? Wb[l] : nullptr;
+        a.b[l] = l <= L ? b[l] : nullptr;
+        if (l <= L && (!a.W[l] || !a.b[l])) return hipErrorInvalidValue;
+    }
+    a.Wv = Wv;
+    a.bv = bv;
+    a.S = S;
+    a.M = M;
+    a.T = T;
+    a.C = C;
+    a.L = L;
+    a.N = N;
+    a.Kp0 = Kp0;
+    a.ldv = ldv;
+    a.ntiles = (T + kFT - 1) / kFT;
+    const dim3 grid(a.ntiles, S);
+    switch (C) {
+        case 16: hipLaunchKernelGGL(net_fused_fwd_kernel<16>, grid, dim3(256), 0, s, a); break;
+        case 32: hipLaunchKernelGGL(net_fused_fwd_kernel<32>, grid, dim3(256), 0, s, a); break;
+        case 48: hipLaunchKernelGGL(net_fused_fwd_kernel<48>, grid, dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(net_fused_fwd_kernel<64>, grid, dim3(256), 0, s, a); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(pool_tiles_kernel, dim3((S * C + 255) / 256), dim3(256), 0, s, part, S, a.ntiles, C, T,
+                       pooled);
     return hipGetLastError();
 }
 

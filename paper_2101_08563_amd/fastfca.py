@@ -57,6 +57,8 @@ SIGNATURES = {
     "fastfca_net_mean_t": (_i, [_vp, _i, _i, _vp, _vp]),
     "fastfca_net_mean_t_bwd": (_i, [_vp, _i, _i, _vp, _vp]),
     "fastfca_net_linear_fwd": (_i, [_vp, _i, _i, _vp, _vp, _i, _vp, _vp]),
+    "fastfca_net_forward_fused": (_i, [_vp, _i, _i, _i, _i, _i, _i, _vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp,
+                                       _vp]),
     "fastfca_net_linear_bwd": (_i, [_vp, _i, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp]),
     "fastfca_net_pit_loss": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, ctypes.c_float, _vp, _vp, _vp, _vp, _vp]),
     "fastfca_net_adamw": (_i, [_vp, _vp, _vp, _vp, _u64, ctypes.c_float, ctypes.c_float, ctypes.c_float,

@@ -141,6 +141,33 @@ class ConvNet:
             self._cache = (feat, hs, pres, pooled)
         return lv, ll
 
+    def fused_ok(self):
+        """Shapes the one-launch inference kernel takes."""
+        return self.C % 16 == 0 and self.C <= 64 and self.L <= 8 and self.N <= 8 and self.M <= 4
+
+    def forward_fused(self, feat):
+        """Inference forward in one launch (activations kept in LDS per time
+        tile), feat [S, M, T] float32 -> (lv [S, N, T], ll [S, N*M])."""
+        S, M, T = feat.shape
+        C, L, N = self.C, self.L, self.N
+        dev = feat.device
+        feat = feat.contiguous()
+        ntiles = (T + 63) // 64
+        lv = torch.empty((S, N, T), dtype=torch.float32, device=dev)
+        part = torch.empty((S * ntiles * C,), dtype=torch.float32, device=dev)
+        pooled = torch.empty((S, C), dtype=torch.float32, device=dev)
+        wb = (ctypes.c_void_p * (L + 1))(*[self.Wb[i].data_ptr() for i in range(L + 1)])
+        bb = (ctypes.c_void_p * (L + 1))(*[self.b[i].data_ptr() for i in range(L + 1)])
+        wv = self.W[L + 1]
+        _chk(self.lib.fastfca_net_forward_fused(_ptr(feat), S, M, T, C, L, N, ctypes.cast(wb, ctypes.c_void_p),
+                                                ctypes.cast(bb, ctypes.c_void_p), _kp(M * 5), _ptr(wv),
+                                                wv.shape[1], _ptr(self.b[L + 1]), _ptr(lv), _ptr(part),
+                                                _ptr(pooled), _stream(self.stream)), self.lib)
+        ll = torch.empty((S, N * M), dtype=torch.float32, device=dev)
+        _chk(self.lib.fastfca_net_linear_fwd(_ptr(pooled), S, C, _ptr(self.Wl), _ptr(self.bl), N * M, _ptr(ll),
+                                             _stream(self.stream)), self.lib)
+        return lv, ll
+
     # -------------------------------------------------------------- backward
     def zero_grad(self):
         for g in self.grads:
@@ -243,7 +270,7 @@ def warm_init(net, x, stream=None, chunk=1024):
     F = x.shape[0]
     lvs, lls = [], []
     for a in range(0, F, chunk):
-        lv, ll = net.forward(feat[a:a + chunk], keep=False)
+        lv, ll = net.forward_fused(feat[a:a + chunk]) if net.fused_ok() else net.forward(feat[a:a + chunk], keep=False)
         lvs.append(lv)
         lls.append(ll)
     lv = torch.cat(lvs) if len(lvs) > 1 else lvs[0]

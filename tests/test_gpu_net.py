@@ -166,3 +166,21 @@ def test_gpu_synthetic_mixture_generator():
     assert torch.equal(a, b) and not torch.equal(a, c)
     p = (a.abs() ** 2).mean().item()
     assert abs(p / (3 * 8 * 1.05) - 1.0) < 0.1, p
+
+
+@pytest.mark.parametrize("S,T,C,L", [(3, 130, 16, 2), (2, 64, 64, 2), (5, 1000, 32, 2), (4, 37, 64, 6),
+                                     (2, 300, 48, 8), (3, 1, 16, 1)])
+def test_fused_forward_matches_layerwise_and_fp64(S, T, C, L):
+    """The one-launch inference forward against the layer-by-layer forward
+    (same BF16 operands; the head is FP32 in the fused kernel) and the FP64
+    reference; T below, at and across 64-frame tiles, the deepest L."""
+    M, N = 2, 3
+    net, p = _net_and_ref(M, N, C, L, seed=L)
+    feat = np.random.default_rng(2 + L).standard_normal((S, M, T)).astype(np.float32)
+    assert net.fused_ok()
+    flv, fll = net.forward_fused(t(feat))
+    lv, ll = net.forward(t(feat), keep=False)
+    rlv, rll, _ = net_ref.forward(p, feat.astype(np.float64), L)
+    assert rel(flv.cpu(), lv.cpu()) < 1e-2 and rel(fll.cpu(), ll.cpu()) < 1e-2
+    assert rel(flv.cpu(), rlv) < 2e-2
+    assert rel(fll.cpu(), rll) < 2e-2
