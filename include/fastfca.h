@@ -356,7 +356,7 @@ int fastfca_net_mean_t_bwd(const float *dpooled, int SC, int T, float *dH, void 
  * operands and FP32 accumulation as fastfca_net_conv_fwd; the head in FP32).
  *   feat    device [S][M][T] float32 features, M <= 4
  *   Wb, b   HOST arrays of L + 1 device pointers: packed BF16 weights of the
- *           kernel-5 layers (layer 0 [C][Kp0], Kp0 a multiple of 16 >= 5 M;
+ *           kernel-5 layers (layer 0 [C][Kp0], Kp0 = 16 or 32, >= 5 M;
  *           layers 1..L [C][5 C]) and their FP32 biases [C]
  *   Wv, bv  device FP32 head weights [N][ldv] (entry c of row n, ldv >= C)
  *           and biases [N], N <= 8

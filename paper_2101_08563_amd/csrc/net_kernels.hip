@@ -227,7 +227,9 @@ __global__ void __launch_bounds__(256) net_fused_fwd_kernel(FusedNetArgs a) {
     const int W0 = kFT + 2 * H;
     const int t0 = tile * kFT;
     const int fr0 = t0 - H;  // frame of row 0
-    for (int i = tid; i < 2 * kFRows * (kMaxC + 4) / 2; i += 256) reinterpret_cast<uint32_t *>(&hb[0][0][0])[i] = 0u;
+    static_assert((2 * kFRows * (kMaxC + 4) * 2) % 16 == 0, "16-byte clears");
+    for (int i = tid; i < 2 * kFRows * (kMaxC + 4) * 2 / 16; i += 256)
+        reinterpret_cast<uint4 *>(&hb[0][0][0])[i] = make_uint4(0u, 0u, 0u, 0u);
     for (int i = tid; i < kFRows * 2; i += 256) reinterpret_cast<uint32_t *>(&fb[0][0])[i] = 0u;
     for (int i = tid; i < a.N * C; i += 256) wvs[i / C][i % C] = a.Wv[static_cast<size_t>(i / C) * a.ldv + i % C];
     for (int i = tid; i < (L + 1) * C; i += 256) bs[i / C][i % C] = a.b[i / C][i % C];
@@ -274,19 +276,33 @@ __global__ void __launch_bounds__(256) net_fused_fwd_kernel(FusedNetArgs a) {
         const uint16_t *Wl = a.W[0] + static_cast<size_t>(16 * w + li) * Kp + 4 * lq;
         const int lo = 2, hi = W0 - 2;
         const int nblk = (hi - lo + 15) / 16;
+        // the lane's (tap, channel) of each of its k entries: k blocks of 16,
+        // at most two since 5 M <= 20
+        int gk[2][4], gc[2][4];
+        bool gv[2][4];
+        bf16x4 af0[2];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            af0[kb] = kb < Kp / 16 ? *reinterpret_cast<const bf16x4 *>(Wl + 16 * kb) : bf16x4{0, 0, 0, 0};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int kk = 16 * kb + 4 * lq + q;
+                gv[kb][q] = kk < 5 * M;
+                gk[kb][q] = gv[kb][q] ? kk / M : 0;
+                gc[kb][q] = gv[kb][q] ? kk - (kk / M) * M : 0;
+            }
+        }
         for (int j = 0; j < nblk; ++j) {
             f32x4 c = f32x4{0.f, 0.f, 0.f, 0.f};
-            for (int kb = 0; kb < Kp / 16; ++kb) {
-                const bf16x4 af = *reinterpret_cast<const bf16x4 *>(Wl + 16 * kb);
-                const int rb = lo + 16 * j + li - 2;
+            const int rb = lo + 16 * j + li - 2;
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                if (kb >= Kp / 16) break;
                 bf16x4 bq;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int kk = 16 * kb + 4 * lq + q;
-                    const int k = kk / M, ci = kk - k * M;
-                    bq[q] = kk < 5 * M ? static_cast<short>(fb[rb + k][ci]) : 0;
-                }
-                c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bq, c, 0, 0, 0);
+                for (int q = 0; q < 4; ++q)
+                    bq[q] = gv[kb][q] ? static_cast<short>(fb[rb + gk[kb][q]][gc[kb][q]]) : 0;
+                c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af0[kb], bq, c, 0, 0, 0);
             }
             store(0, j, lo, hi, c, f32x4{0.f, 0.f, 0.f, 0.f}, hb[0]);
         }
@@ -345,6 +361,7 @@ __global__ void __launch_bounds__(256) net_fused_fwd_kernel(FusedNetArgs a) {
         const int t = t0 + i;
         if (t < T) {
             float y = a.bv[n];
+#pragma unroll
             for (int c = 0; c < C; ++c) y = fmaf(wvs[n][c], hf[H + i][c], y);
             a.lv[(static_cast<size_t>(s) * a.N + n) * T + t] = y;
         }
@@ -861,7 +878,7 @@ hipError_t net_forward_fused(const float *feat, int S, int M, int T, int C, int 
                              const uint16_t *const *Wb, const float *const *b, int Kp0, const float *Wv, int ldv,
                              const float *bv, float *lv, float *part, float *pooled, hipStream_t s) {
     if (S < 1 || T < 1 || M < 1 || M > 4 || C < 16 || C > kMaxC || C % 16 || L < 0 || L > kFMaxL || N < 1 ||
-        N > kFMaxN || Kp0 % 16 || Kp0 < 5 * M || Kp0 > kMaxKp || 5 * C > kMaxKp || ldv < C)
+        N > kFMaxN || Kp0 % 16 || Kp0 < 5 * M || Kp0 > 32 || 5 * C > kMaxKp || ldv < C)
         return hipErrorInvalidValue;
     FusedNetArgs a;
     a.feat = feat;
