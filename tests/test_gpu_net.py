@@ -168,13 +168,14 @@ def test_gpu_synthetic_mixture_generator():
     assert abs(p / (3 * 8 * 1.05) - 1.0) < 0.1, p
 
 
-@pytest.mark.parametrize("S,T,C,L", [(3, 130, 16, 2), (2, 64, 64, 2), (5, 1000, 32, 2), (4, 37, 64, 6),
-                                     (2, 300, 48, 8), (3, 1, 16, 1)])
-def test_fused_forward_matches_layerwise_and_fp64(S, T, C, L):
+@pytest.mark.parametrize("S,T,C,L,M,N", [(3, 130, 16, 2, 2, 3), (2, 64, 64, 2, 2, 3), (5, 1000, 32, 2, 2, 3),
+                                         (4, 37, 64, 6, 2, 3), (2, 300, 48, 8, 2, 3), (3, 1, 16, 1, 2, 3),
+                                         (2, 200, 32, 0, 2, 3), (3, 150, 32, 2, 4, 6), (2, 90, 16, 3, 3, 4)])
+def test_fused_forward_matches_layerwise_and_fp64(S, T, C, L, M, N):
     """The one-launch inference forward against the layer-by-layer forward
     (same BF16 operands; the head is FP32 in the fused kernel) and the FP64
-    reference; T below, at and across 64-frame tiles, the deepest L."""
-    M, N = 2, 3
+    reference; T below, at and across 64-frame tiles, no residual layer and
+    the deepest L, and input layers of one and two 16-wide k blocks (M = 2..4)."""
     net, p = _net_and_ref(M, N, C, L, seed=L)
     feat = np.random.default_rng(2 + L).standard_normal((S, M, T)).astype(np.float32)
     assert net.fused_ok()
