@@ -257,14 +257,15 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
     float vr[BPT][N];
     float U[BPT][M];
     float mk[BPT];
-    // M = 2 keeps sigma^2 and 1/sigma^2 of every bin from phase A through
-    // phase C: source 1 uses them as they are, and each later source updates
-    // sigma^2 by the change of its own term (two FMAs instead of N). Phase A
-    // recomputes them from L and H every iteration, so rounding does not
-    // accumulate across iterations. Wider M would lose occupancy to the
-    // 2 M BPT registers (and M = 2 with eight bins per thread beyond four
-    // sources).
-    constexpr bool kKeep = (M == 2) && (BPT <= 4 || N <= 4);
+    // M = 2 and M = 4 (four bins per thread) keep sigma^2 and 1/sigma^2 of
+    // every bin from phase A through phase C: source 1 uses them as they are,
+    // and each later source updates sigma^2 by the change of its own term
+    // (two FMAs instead of N). Phase A recomputes them from L and H every
+    // iteration, so rounding does not accumulate across iterations. The
+    // other shapes would lose occupancy to the 2 M BPT registers (M = 3 drops
+    // from three waves per SIMD to two; M = 2 with eight bins per thread
+    // beyond four sources, from two to one).
+    constexpr bool kKeep = ((M == 2) && (BPT <= 4 || N <= 4)) || (M == 4 && BPT == 4);
     float sg[kKeep ? BPT : 1][M];
     float wr[kKeep ? BPT : 1][M];
 #pragma unroll
