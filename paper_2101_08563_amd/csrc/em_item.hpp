@@ -561,9 +561,12 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
         // so the L update is the T-mean of e and the H update is
         //   h <- h * (1/M) sum_m e_m / l_new,m,
         // which needs no reciprocal of h.
+        // a non-positive or non-finite L is recorded and acted on after the
+        // last source, so no branch waits on the check inside the loop (the
+        // failing frequency's state is left as it is then)
+        bool bad = false;
 #pragma unroll
         for (int n = 0; n < N; ++n) {
-            if (status != ST_OK) continue;
             float part[M];
             float e[BPT][M];
             float l2[M];
@@ -610,10 +613,7 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                 c[m] = rcp(l * static_cast<float>(M));
             }
             buf ^= 1;
-            if (!good) {
-                status = ST_NONFINITE;
-                continue;
-            }
+            bad = bad || !good;
 #pragma unroll
             for (int k = 0; k < BPT; ++k) {
                 float s = 0.0f;
@@ -633,6 +633,7 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                 }
             }
         }
+        if (bad) status = ST_NONFINITE;
         if (status != ST_OK) break;
     }
 
