@@ -6,12 +6,13 @@ namespace ffca {
 // Register budget: a launch with BPT bins per thread uses at most 2048 / BPT
 // threads (kMaxThreadsFor), which lets the compiler give each lane up to
 // 128 (BPT 2), 256 (BPT 4) or 512 (BPT 8) VGPRs.
-// M = 3 at eight bins per thread is held to 256 VGPRs (two waves per SIMD);
-// at N = 5 that costs a few spills and still runs 26 % faster than one wave
-// per SIMD at 275 VGPRs (513 frequencies, T = 2000).
+// M = 3 at eight bins per thread with up to five sources is held to 256
+// VGPRs (two waves per SIMD); at N = 5 that costs some spills and still runs
+// 26 % faster than one wave per SIMD at 275 VGPRs (513 frequencies,
+// T = 2000). More sources would spill too much.
 template <int M, int N, int BPT>
 __global__ void __launch_bounds__(kResidentBins / BPT)
-    __attribute__((amdgpu_waves_per_eu(M == 3 && BPT == 8 ? 2 : 1))) em_kernel(EmLaunch a) {
+    __attribute__((amdgpu_waves_per_eu(M == 3 && BPT == 8 && N <= 5 ? 2 : 1))) em_kernel(EmLaunch a) {
     __shared__ EmSmem<M * M * M, 2 * N * M, wave_slots(BPT)> sm;
     const WorkItem &it = a.items[blockIdx.x];
     if (*it.status != ST_OK) return;  // frozen after an earlier failure
