@@ -182,99 +182,4 @@ __device__ __forceinline__ cd cdiv(cd a, cd b) {
 __device__ __forceinline__ cd ld(const double2 &a) { return cd{a.x, a.y}; }
 __device__ __forceinline__ double2 st(cd a) { return make_double2(a.re, a.im); }
 
-// Solve A z = b (M x M, complex double, in registers) by Gaussian elimination
-// with partial pivoting; z overwrites b. Pivot rows are swapped through
-// compile-time-indexed selects so the arrays stay in registers. Returns false
-// if a pivot falls below tol * max|A|.
-template <int M>
-__device__ __forceinline__ bool solve_pp(cd (&A)[M][M], cd (&b)[M], double tol) {
-    double amax2 = 0.0;
-#pragma unroll
-    for (int r = 0; r < M; ++r)
-#pragma unroll
-        for (int c = 0; c < M; ++c) amax2 = fmax(amax2, abs2(A[r][c]));
-    if (!(amax2 > 0.0) || !(amax2 < INFINITY)) return false;
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        int p = k;
-        double best = abs2(A[k][k]);
-#pragma unroll
-        for (int i = k + 1; i < M; ++i) {
-            double a = abs2(A[i][k]);
-            if (a > best) {
-                best = a;
-                p = i;
-            }
-        }
-        if (!(best >= tol * tol * amax2)) return false;
-#pragma unroll
-        for (int i = k + 1; i < M; ++i) {
-            if (p == i) {
-#pragma unroll
-                for (int j = 0; j < M; ++j) {
-                    cd t = A[k][j];
-                    A[k][j] = A[i][j];
-                    A[i][j] = t;
-                }
-                cd t = b[k];
-                b[k] = b[i];
-                b[i] = t;
-            }
-        }
-#pragma unroll
-        for (int i = k + 1; i < M; ++i) {
-            cd l = cdiv(A[i][k], A[k][k]);
-#pragma unroll
-            for (int j = k; j < M; ++j) A[i][j] = A[i][j] - l * A[k][j];
-            b[i] = b[i] - l * b[k];
-        }
-    }
-#pragma unroll
-    for (int i = M - 1; i >= 0; --i) {
-        cd s = b[i];
-#pragma unroll
-        for (int j = i + 1; j < M; ++j) s = s - A[i][j] * b[j];
-        b[i] = cdiv(s, A[i][i]);
-    }
-    return true;
-}
-
-// ln|det A|^2 by elimination with partial pivoting (A is destroyed).
-template <int M>
-__device__ __forceinline__ double logabsdet2(cd (&A)[M][M]) {
-    double acc = 0.0;
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        int p = k;
-        double best = abs2(A[k][k]);
-#pragma unroll
-        for (int i = k + 1; i < M; ++i) {
-            double a = abs2(A[i][k]);
-            if (a > best) {
-                best = a;
-                p = i;
-            }
-        }
-#pragma unroll
-        for (int i = k + 1; i < M; ++i) {
-            if (p == i) {
-#pragma unroll
-                for (int j = 0; j < M; ++j) {
-                    cd t = A[k][j];
-                    A[k][j] = A[i][j];
-                    A[i][j] = t;
-                }
-            }
-        }
-#pragma unroll
-        for (int i = k + 1; i < M; ++i) {
-            cd l = cdiv(A[i][k], A[k][k]);
-#pragma unroll
-            for (int j = k; j < M; ++j) A[i][j] = A[i][j] - l * A[k][j];
-        }
-        acc += log(abs2(A[k][k]));
-    }
-    return acc;
-}
-
 }  // namespace ffca
