@@ -211,13 +211,15 @@ def test_invalid_inputs_report_errors():
     assert e.value.code == -1
 
 
-def test_zero_frequency_is_reported_singular():
-    """An all-zero frequency makes every Q_m zero: the IP system is singular;
-    the failure names the frequency and leaves the others untouched."""
-    x, P0, lam0, v0 = make_case(5, 80, 2, 3, config_id=28)
+@pytest.mark.parametrize("M,N", [(2, 3), (3, 4), (4, 6)])
+def test_zero_frequency_is_reported_singular(M, N):
+    """An all-zero frequency makes every Q_m zero: the IP system is singular
+    (the M = 2 closed form and the lane-parallel sweep for M = 3, 4); the
+    failure names the frequency and leaves the others untouched."""
+    x, P0, lam0, v0 = make_case(5, 80, M, N, config_id=28)
     x[3] = 0.0
     xd, Pd, ld, vd = to_dev(x, P0, lam0, v0)
-    ctx = FastFCA(xd, 3, Pd, ld, vd)
+    ctx = FastFCA(xd, N, Pd, ld, vd)
     ctx.em_step(5)
     with pytest.raises(FastFCAError) as e:
         ctx.sync()
@@ -226,7 +228,7 @@ def test_zero_frequency_is_reported_singular():
     ctx.close()
     keep = [0, 1, 2, 4]
     Po, lo, vo, _ = oracle.fit(x[keep], P0[keep], lam0[keep], v0[keep], 5)
-    assert rel(v[keep], vo) < 1e-4
+    assert rel(v[keep], vo) < 1e-4 and rel(P[keep], Po) < 1e-4
 
 
 @pytest.mark.parametrize("M,N,T,F", [(2, 3, 1000, 64), (3, 4, 700, 9), (4, 6, 400, 7), (2, 2, 77, 5),
