@@ -28,7 +28,7 @@
 
 #include "device.hpp"
 #include "internal.hpp"
-#include "ip_wave.hpp"
+#include "ip_sm.hpp"
 
 namespace ffca {
 
@@ -58,7 +58,7 @@ struct EmSmem {
     double qtot[RQ];
     double2 Pd[kMaxM * kMaxM];
     float2 P32[kMaxM * kMaxM];
-    IpLds<kMaxM> ip;             // IP scratch (lane-parallel sweep, M = 3, 4)
+    IpSmLds<kMaxM> ip;           // IP scratch (M = 3, 4)
     double ldet[2];              // ln|det P|^2 of the IP of iterations of each parity
     int flag;                    // IP status
     int flag_ll;                 // likelihood status
@@ -413,8 +413,8 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                 if (lane < NQ) sm.qtot[lane] = static_cast<double>(sum_waves<NW>(sm.redq[lane], nw)) * invT;
                 __threadfence_block();
                 __builtin_amdgcn_wave_barrier();
-                // lane-parallel IP sweep in double precision
-                status = ip_wave<M, kMaxM>(sm.qtot, sm.Pd, sm.P32, sm.ip, ldet);
+                // IP sweep in double precision through the inverses
+                status = ip_sm<M, kMaxM>(sm.qtot, sm.Pd, sm.P32, sm.ip, ldet);
             }
             if (status == ST_OK) {
                 ldet_prev = ldet;

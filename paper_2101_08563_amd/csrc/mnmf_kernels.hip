@@ -36,7 +36,7 @@ struct MnmfSmem {
     double qtot[M * M * M];
     double2 Pd[kMaxM * kMaxM];
     float2 P32[kMaxM * kMaxM];
-    IpLds<kMaxM> ip;
+    IpSmLds<kMaxM> ip;
     float t[kMnmfKMax * N];
     int flag;
 };
@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(kResidentBins / BPT) mnmf_freq_kernel(MnmfLaun
             if (lane < NQ) sm.qtot[lane] = static_cast<double>(sum_slots<NR>(sm.redq[lane])) * invT;
             __threadfence_block();
             __builtin_amdgcn_wave_barrier();
-            st = ip_wave<M, kMaxM>(sm.qtot, sm.Pd, sm.P32, sm.ip, ldet);
+            st = ip_sm<M, kMaxM>(sm.qtot, sm.Pd, sm.P32, sm.ip, ldet);
         }
         if (lane == 0) {
             sm.flag = st;
