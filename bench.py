@@ -51,7 +51,7 @@ def em_bytes_per_bin(M: int, N: int) -> int:
     return 8 * M + 8 * N
 
 
-KERNEL_FILES = ["em_item.hpp", "em_kernel.hip", "device.hpp", "internal.hpp"]
+KERNEL_FILES = ["em_item.hpp", "em_kernel.hip", "device.hpp", "internal.hpp", "ip_sm.hpp", "ip_wave.hpp"]
 
 
 def kernel_source_hash() -> str:
