@@ -97,6 +97,25 @@ def test_classes_and_ragged_tails(M, N, T):
     check_against_oracle(x, P0, lam0, v0, 20, g, "M%d N%d T%d" % (M, N, T))
 
 
+def general_start(F, M, seed):
+    """A seeded complex P_0 = I + 0.5 (A + iB), A and B standard normal, per frequency."""
+    rng = np.random.default_rng(seed)
+    return np.eye(M) + 0.5 * (rng.standard_normal((F, M, M)) + 1j * rng.standard_normal((F, M, M)))
+
+
+@pytest.mark.parametrize("M,N,rank,diffuse", [(3, 4, 3, 1e-2), (4, 6, 4, 1e-2), (4, 5, 2, 1e-1), (4, 6, 4, 1e-3),
+                                              (3, 4, 1, 1e-3)])
+def test_ip_from_general_P_and_ill_conditioned_mixtures(M, N, rank, diffuse):
+    """The M = 3, 4 sweep works through explicit inverses of P and of the Q_m:
+    start from a general complex P (not the identity) and use mixtures whose
+    spatial covariances are close to low rank (small diffuse part)."""
+    F, T, iters = 7, 300, 10
+    x, _, lam0, v0 = make_case(F, T, M, N, rank=rank, diffuse=diffuse, config_id=30 + M, mixture_id=N)
+    P0 = general_start(F, M, 1000 * M + N)
+    g = run_gpu(x, P0, lam0, v0, iters)
+    check_against_oracle(x, P0, lam0, v0, iters, g, "general P0, M%d N%d rank %d diffuse %g" % (M, N, rank, diffuse))
+
+
 @pytest.mark.parametrize("threads,bpt", [(64, 8), (128, 8), (256, 4), (512, 2), (1024, 2)])
 def test_launch_configurations_agree(threads, bpt):
     """The result does not depend on the launch shape beyond rounding."""
