@@ -66,6 +66,7 @@ struct IpSmLds {
 template <int M, int MM>
 __device__ __noinline__ int ip_sm(const double *qtot, double2 *Pd, float2 *P32, IpSmLds<MM> &w, double &ldet) {
     static_assert(M >= 2 && M <= MM, "ip_sm shape");
+    static_assert(M <= 4, "the sums over c fold over the four 16-lane rows");
     constexpr int M2 = M * M;
     constexpr int W2 = 2 * M;
     constexpr int NQ = M * M2;           // entries of the Q_m
