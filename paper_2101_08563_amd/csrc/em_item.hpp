@@ -172,9 +172,17 @@ __device__ __forceinline__ float sum_waves(const float *p, int nw) {
 //   Q^{-1} = adj(Q) / det Q.
 // With u = adj(Q) b and s = b^H u, eq:ip2's normalization w^H Q w = 1 makes
 //   w = u d / sqrt(s det(Q) |d|^2),
-// one reciprocal square root per column and no division. The system is
-// taken as singular when |det(P^H Q)|^2 = |d|^2 det(Q)^2 falls below
-// tol^2 (|P|_F^2 |Q|_F^2)^2, the fourth power of a bound on its largest entry.
+// one reciprocal square root per column and no division. The second column
+// does not wait for the first one's normalization: with the new first column
+// w_1 = c u_1 (c = d / sqrt(s_1 det(Q_1) |d|^2)), the second column's b is
+// conj(c) beta, beta = conj(-u_1[1], u_1[0]), and the new determinant is
+// c delta, delta = u_1[0] P11 - P01 u_1[1], so that
+//   w_2 = nu delta / sqrt(sigma det(Q_2) |delta|^2),
+//   nu = adj(Q_2) beta, sigma = beta^H nu,
+// in which c cancels. The system is taken as singular when
+// |det(P^H Q)|^2 = |d|^2 det(Q)^2 falls below tol^2 (|P|_F^2 |Q|_F^2)^2, the
+// fourth power of a bound on its largest entry, with P the matrix each
+// column's solve sees.
 // q: the 8 Hermitian parameters (Q_1 then Q_2) of T Q_m, the sums before
 // the division by T; qscale = sqrt(T). Scaling Q by T scales u and s by T and
 // det Q by T^2, so w of the scaled sums is w / sqrt(T), and the pivot test
@@ -183,47 +191,67 @@ __device__ __forceinline__ float sum_waves(const float *p, int nw) {
 // stored unless both columns pass.
 template <class Smem>
 __device__ __forceinline__ int ip_sweep_reg2(Smem &sm, const double (&q)[8], double qscale, double &ldet) {
-    cd P00 = ld(sm.Pd[0]), P01 = ld(sm.Pd[1]), P10 = ld(sm.Pd[2]), P11 = ld(sm.Pd[3]);
-    int stat = ST_OK;
+    const cd P00 = ld(sm.Pd[0]), P01 = ld(sm.Pd[1]), P10 = ld(sm.Pd[2]), P11 = ld(sm.Pd[3]);
+    // the Q_m terms of both columns
+    double dq[2], nq[2];
+    bool fin[2];
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
         const double q00 = q[4 * m + 0], q11 = q[4 * m + 1];
         const cd q01 = cmk(q[4 * m + 2], q[4 * m + 3]);
-        const bool fin = (fabs(q00) < INFINITY) && (fabs(q11) < INFINITY) && (abs2(q01) < INFINITY);
-        const cd b0 = m == 0 ? conjd(P11) : cmk(-P10.re, P10.im);
-        const cd b1 = m == 0 ? cmk(-P01.re, P01.im) : conjd(P00);
-        const cd u0 = q11 * b0 - q01 * b1;
-        const cd u1 = q00 * b1 - conjd(q01) * b0;
-        const double sb = (conjd(b0) * u0 + conjd(b1) * u1).re;
-        const double dq = q00 * q11 - abs2(q01);
-        const cd d = P00 * P11 - P01 * P10;
-        const double d2 = abs2(d);
-        const double nq = q00 * q00 + q11 * q11 + 2.0 * abs2(q01);
-        const double np = (abs2(P00) + abs2(P01)) + (abs2(P10) + abs2(P11));
-        const double t = sb * dq * d2;
-        const bool piv = (d2 * dq * dq >= kPivotTol * kPivotTol * (np * nq) * (np * nq)) && (t > 0.0) && (t < INFINITY);
-        stat = stat != ST_OK ? stat : (!fin ? ST_NONFINITE : (!piv ? ST_SINGULAR : ST_OK));
-        const double r = rsqrt_d(t) * qscale;
-        const cd w0 = r * (u0 * d), w1 = r * (u1 * d);
-        if (m == 0) {
-            P00 = w0;
-            P10 = w1;
-        } else {
-            P01 = w0;
-            P11 = w1;
-        }
+        fin[m] = (fabs(q00) < INFINITY) && (fabs(q11) < INFINITY) && (abs2(q01) < INFINITY);
+        dq[m] = q00 * q11 - abs2(q01);
+        nq[m] = q00 * q00 + q11 * q11 + 2.0 * abs2(q01);
     }
+    auto adjq = [&](int m, cd b0, cd b1, cd &u0, cd &u1) {
+        const double q00 = q[4 * m + 0], q11 = q[4 * m + 1];
+        const cd q01 = cmk(q[4 * m + 2], q[4 * m + 3]);
+        u0 = q11 * b0 - q01 * b1;
+        u1 = q00 * b1 - conjd(q01) * b0;
+    };
+    auto pivot_ok = [&](int m, double d2, double np, double t) {
+        return (d2 * dq[m] * dq[m] >= kPivotTol * kPivotTol * (np * nq[m]) * (np * nq[m])) && (t > 0.0) &&
+               (t < INFINITY);
+    };
+    // first column
+    cd a0, a1;
+    adjq(0, conjd(P11), cmk(-P01.re, P01.im), a0, a1);
+    const double sb = (P11 * a0 - P01 * a1).re;  // b^H u with b = conj(P11, -P01)
+    const cd d = P00 * P11 - P01 * P10;
+    const double d2 = abs2(d);
+    const double np = (abs2(P00) + abs2(P01)) + (abs2(P10) + abs2(P11));
+    const double t = sb * dq[0] * d2;
+    // second column from u of the first: beta = conj(-a1, a0)
+    cd n0, n1;
+    const cd be0 = cmk(-a1.re, a1.im), be1 = conjd(a0);
+    adjq(1, be0, be1, n0, n1);
+    const double sg = (conjd(be0) * n0 + conjd(be1) * n1).re;
+    const cd de = a0 * P11 - P01 * a1;
+    const double de2 = abs2(de);
+    const double t2 = sg * dq[1] * de2;
+    // both normalizations
+    const double r = rsqrt_d(t) * qscale;
+    const cd c = r * d;
+    const cd W00 = a0 * c, W10 = a1 * c;
+    const double r2 = rsqrt_d(t2) * qscale;
+    const cd W01 = r2 * (n0 * de), W11 = r2 * (n1 * de);
+    // the second solve's pivot test on the P it sees: [w_1 | p_2]
+    const double c2 = abs2(c);
+    const double np2 = c2 * (abs2(a0) + abs2(a1)) + (abs2(P01) + abs2(P11));
+    int stat = !fin[0] ? ST_NONFINITE : (!pivot_ok(0, d2, np, t) ? ST_SINGULAR : ST_OK);
+    const int stat2 = !fin[1] ? ST_NONFINITE : (!pivot_ok(1, c2 * de2, np2, t2) ? ST_SINGULAR : ST_OK);
+    stat = stat != ST_OK ? stat : stat2;
     if (stat != ST_OK) return stat;
     // ln|det P|^2 for the likelihood trace (single precision logarithm)
-    ldet = static_cast<double>(ln_fast(static_cast<float>(abs2(P00 * P11 - P01 * P10))));
-    sm.Pd[0] = st(P00);
-    sm.Pd[1] = st(P01);
-    sm.Pd[2] = st(P10);
-    sm.Pd[3] = st(P11);
-    sm.P32[0] = make_float2(static_cast<float>(P00.re), static_cast<float>(P00.im));
-    sm.P32[1] = make_float2(static_cast<float>(P01.re), static_cast<float>(P01.im));
-    sm.P32[2] = make_float2(static_cast<float>(P10.re), static_cast<float>(P10.im));
-    sm.P32[3] = make_float2(static_cast<float>(P11.re), static_cast<float>(P11.im));
+    ldet = static_cast<double>(ln_fast(static_cast<float>(abs2(W00 * W11 - W01 * W10))));
+    sm.Pd[0] = st(W00);
+    sm.Pd[1] = st(W01);
+    sm.Pd[2] = st(W10);
+    sm.Pd[3] = st(W11);
+    sm.P32[0] = make_float2(static_cast<float>(W00.re), static_cast<float>(W00.im));
+    sm.P32[1] = make_float2(static_cast<float>(W01.re), static_cast<float>(W01.im));
+    sm.P32[2] = make_float2(static_cast<float>(W10.re), static_cast<float>(W10.im));
+    sm.P32[3] = make_float2(static_cast<float>(W11.re), static_cast<float>(W11.im));
     return ST_OK;
 }
 
