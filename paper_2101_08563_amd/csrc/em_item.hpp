@@ -189,9 +189,12 @@ __device__ __forceinline__ float sum_waves(const float *p, int nw) {
 // is scale free: one multiplication per column replaces eight scalings.
 // The checks are folded into one status without branches; nothing is
 // stored unless both columns pass.
+// P: the current P (row-major), read by the caller before the slot sums so
+// that both LDS reads are in flight together.
 template <class Smem>
-__device__ __forceinline__ int ip_sweep_reg2(Smem &sm, const double (&q)[8], double qscale, double &ldet) {
-    const cd P00 = ld(sm.Pd[0]), P01 = ld(sm.Pd[1]), P10 = ld(sm.Pd[2]), P11 = ld(sm.Pd[3]);
+__device__ __forceinline__ int ip_sweep_reg2(Smem &sm, const cd (&P)[4], const double (&q)[8], double qscale,
+                                             double &ldet) {
+    const cd P00 = P[0], P01 = P[1], P10 = P[2], P11 = P[3];
     // the Q_m terms of both columns
     double dq[2], nq[2];
     bool fin[2];
@@ -430,13 +433,14 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
         if (wid == 0 && !last) {
             double ldet = 0.0;
             if constexpr (M == 2) {
-                // lane i sums value i over the row slots, then every lane
-                // reads all eight sums from registers
+                // lane i sums value i % 8 over the row slots, then every lane
+                // reads the eight sums of lanes 0-7 from registers
+                const cd Pc[4] = {ld(sm.Pd[0]), ld(sm.Pd[1]), ld(sm.Pd[2]), ld(sm.Pd[3])};
                 double qs[8];
-                const float mine = lane < 8 ? sum_waves<NW>(sm.redq[lane], nw) : 0.0f;
+                const float mine = sum_waves<NW>(sm.redq[lane & 7], nw);
 #pragma unroll
                 for (int i = 0; i < 8; ++i) qs[i] = static_cast<double>(readlane_f(mine, i));
-                status = ip_sweep_reg2(sm, qs, sqrtT, ldet);
+                status = ip_sweep_reg2(sm, Pc, qs, sqrtT, ldet);
             } else {
                 if (lane < NQ) sm.qtot[lane] = static_cast<double>(sum_waves<NW>(sm.redq[lane], nw)) * invT;
                 __threadfence_block();

@@ -215,11 +215,12 @@ __global__ void __launch_bounds__(kResidentBins / BPT) mnmf_freq_kernel(MnmfLaun
         double ldet = 0.0;
         int st;
         if constexpr (M == 2) {
+            const cd Pc[4] = {ld(sm.Pd[0]), ld(sm.Pd[1]), ld(sm.Pd[2]), ld(sm.Pd[3])};
             double qs[8];
-            const float mine = lane < 8 ? sum_slots<NR>(sm.redq[lane]) : 0.0f;
+            const float mine = sum_slots<NR>(sm.redq[lane & 7]);
 #pragma unroll
             for (int e = 0; e < 8; ++e) qs[e] = static_cast<double>(readlane_f(mine, e));
-            st = ip_sweep_reg2(sm, qs, sqrt(static_cast<double>(T)), ldet);
+            st = ip_sweep_reg2(sm, Pc, qs, sqrt(static_cast<double>(T)), ldet);
         } else {
             if (lane < NQ) sm.qtot[lane] = static_cast<double>(sum_slots<NR>(sm.redq[lane])) * invT;
             __threadfence_block();
