@@ -63,10 +63,11 @@ __device__ bool block_gauss_jordan(double2 (*A)[2 * M], double &ldet, double tol
     return ok;
 }
 
-// One workgroup per frequency: B = P^{-H} (single precision) and ln|det P|^2.
+// One workgroup per frequency: ln|det P|^2 by Gauss-Jordan elimination with
+// partial pivoting in double precision; a singular P is recorded in the
+// frequency's status and its ln|det P|^2 set to NaN.
 template <int M>
-__global__ void __launch_bounds__(kAuxThreads) pinv_kernel(const WorkItem *items, float2 *Bh,
-                                                           double *ldet_out) {
+__global__ void __launch_bounds__(kAuxThreads) ldet_kernel(const WorkItem *items, double *ldet_out) {
     __shared__ double2 A[M][2 * M];
     const WorkItem &it = items[blockIdx.x];
     const int tid = threadIdx.x;
@@ -77,21 +78,10 @@ __global__ void __launch_bounds__(kAuxThreads) pinv_kernel(const WorkItem *items
     __syncthreads();
     double ldet;
     const bool ok = block_gauss_jordan<M>(A, ldet, kPivotTol);
-    if (!ok) {
-        if (tid == 0) *it.status = ST_SINGULAR;
-        if (ldet_out && tid == 0) ldet_out[blockIdx.x] = NAN;
-        return;
+    if (tid == 0) {
+        if (!ok) *it.status = ST_SINGULAR;
+        ldet_out[blockIdx.x] = ok ? ldet : NAN;
     }
-    // B[r][c] = conj(Pinv[c][r])
-    if (Bh) {
-        for (int i = tid; i < M * M; i += blockDim.x) {
-            const int r = i / M, c = i % M;
-            const double2 v = A[c][M + r];
-            Bh[static_cast<size_t>(blockIdx.x) * M * M + i] =
-                make_float2(static_cast<float>(v.x), static_cast<float>(-v.y));
-        }
-    }
-    if (ldet_out && tid == 0) ldet_out[blockIdx.x] = ldet;
 }
 
 // ------------------------------------------------------------------ log-likelihood
@@ -174,10 +164,13 @@ __global__ void __launch_bounds__(kAuxThreads) loglik_kernel(const WorkItem *ite
 // Grid (ceil(Tx / blockDim), F). One thread per TF bin (frame t; its h is
 // that of block t / B):
 //   z = P^H x ;  for each n: y_n = B (g_n .* z),  g_nm = h_n lam_nm / sigma^2_m,
-// with B = P^{-H} from pinv_kernel.
+// with B = P^{-H}. Every workgroup inverts its frequency's P itself (double
+// precision Gauss-Jordan in LDS, a few microseconds that overlap across the
+// grid) instead of reading it from a separate inversion launch; a singular P
+// is recorded in the frequency's status by the workgroup of its first tile.
 template <int M>
-__global__ void __launch_bounds__(kAuxThreads) mwf_kernel(const WorkItem *items,
-                                                          const float2 *Bh, int F, float2 *y) {
+__global__ void __launch_bounds__(kAuxThreads) mwf_kernel(const WorkItem *items, int F, float2 *y) {
+    __shared__ double2 A[M][2 * M];
     __shared__ float2 Ps[M * M];
     __shared__ float2 Bs[M * M];
     __shared__ float lam_s[FFCA_MAXN_AUX * M];
@@ -185,12 +178,26 @@ __global__ void __launch_bounds__(kAuxThreads) mwf_kernel(const WorkItem *items,
     const WorkItem &it = items[f];
     const int tid = threadIdx.x;
     const int T = it.Tx, N = it.N;
+    for (int i = tid; i < M * 2 * M; i += blockDim.x) {
+        const int r = i / (2 * M), c = i % (2 * M);
+        A[r][c] = c < M ? it.P[r * M + c] : make_double2(c - M == r ? 1.0 : 0.0, 0.0);
+    }
     if (tid < M * M) {
         const double2 p = it.P[tid];
         Ps[tid] = make_float2(static_cast<float>(p.x), static_cast<float>(p.y));
-        Bs[tid] = Bh[static_cast<size_t>(f) * M * M + tid];
     }
     for (int i = tid; i < N * M; i += blockDim.x) lam_s[i] = it.lam[i];
+    __syncthreads();
+    double ldet;
+    if (!block_gauss_jordan<M>(A, ldet, kPivotTol)) {
+        if (blockIdx.x == 0 && tid == 0) *it.status = ST_SINGULAR;
+        return;
+    }
+    // B[r][c] = conj(Pinv[c][r])
+    if (tid < M * M) {
+        const double2 v = A[tid % M][M + tid / M];
+        Bs[tid] = make_float2(static_cast<float>(v.x), static_cast<float>(-v.y));
+    }
     __syncthreads();
     const int t = blockIdx.x * blockDim.x + tid;
     if (t >= T) return;
@@ -349,9 +356,8 @@ __global__ void __launch_bounds__(kAuxThreads) seeded_init_kernel(const float2 *
         default: return hipErrorInvalidValue; \
     }
 
-hipError_t launch_pinv(const WorkItem *items, int n_items, int M, float2 *Bh, double *ldet,
-                       hipStream_t s) {
-#define FFCA_CALL(MM) hipLaunchKernelGGL(pinv_kernel<MM>, dim3(n_items), dim3(64), 0, s, items, Bh, ldet)
+hipError_t launch_ldet(const WorkItem *items, int n_items, int M, double *ldet, hipStream_t s) {
+#define FFCA_CALL(MM) hipLaunchKernelGGL(ldet_kernel<MM>, dim3(n_items), dim3(64), 0, s, items, ldet)
     FFCA_M_SWITCH(M, FFCA_CALL)
 #undef FFCA_CALL
     return hipGetLastError();
@@ -366,10 +372,9 @@ hipError_t launch_loglik_terms(const WorkItem *items, int n_items, int M, const 
     return hipGetLastError();
 }
 
-hipError_t launch_mwf_bins(const WorkItem *items, const float2 *Bh, int F, int T, int M,
-                           float2 *y, hipStream_t s) {
+hipError_t launch_mwf_bins(const WorkItem *items, int F, int T, int M, float2 *y, hipStream_t s) {
     dim3 grid((T + kAuxThreads - 1) / kAuxThreads, F);
-#define FFCA_CALL(MM) hipLaunchKernelGGL(mwf_kernel<MM>, grid, dim3(kAuxThreads), 0, s, items, Bh, F, y)
+#define FFCA_CALL(MM) hipLaunchKernelGGL(mwf_kernel<MM>, grid, dim3(kAuxThreads), 0, s, items, F, y)
     FFCA_M_SWITCH(M, FFCA_CALL)
 #undef FFCA_CALL
     return hipGetLastError();

@@ -19,12 +19,10 @@
 #include "mnmf.hpp"
 
 namespace ffca {
-hipError_t launch_pinv(const WorkItem *items, int n_items, int M, float2 *Bh, double *ldet,
-                       hipStream_t s);
+hipError_t launch_ldet(const WorkItem *items, int n_items, int M, double *ldet, hipStream_t s);
 hipError_t launch_loglik_terms(const WorkItem *items, int n_items, int M, const double *ldet,
                                double *ll_f, hipStream_t s);
-hipError_t launch_mwf_bins(const WorkItem *items, const float2 *Bh, int F, int T, int M,
-                           float2 *y, hipStream_t s);
+hipError_t launch_mwf_bins(const WorkItem *items, int F, int T, int M, float2 *y, hipStream_t s);
 hipError_t launch_synth(float2 *x, int F, int T, int M, int N, int K, float delta, uint64_t seed,
                         float *W, float2 *C, hipStream_t s);
 }  // namespace ffca
@@ -46,7 +44,6 @@ struct Problem {
     double2 *P = nullptr;
     double *ldet = nullptr;
     double *llf = nullptr;
-    float2 *Bh = nullptr;
     WorkItem *items = nullptr;  // this mixture's items in frequency order
     int item0 = 0;  // index of frequency 0 in the context's item array
 };
@@ -146,7 +143,6 @@ void free_problem(Problem &p) {
     hipFree(p.P);
     hipFree(p.ldet);
     hipFree(p.llf);
-    hipFree(p.Bh);
     hipFree(p.items);
     p = Problem{};
 }
@@ -357,7 +353,6 @@ int alloc_problem(fastfca_ctx *c, Problem &p) {
     if ((rc = dalloc(c, &p.P, F * M * M)) != FASTFCA_OK) return rc;
     if ((rc = dalloc(c, &p.ldet, F)) != FASTFCA_OK) return rc;
     if ((rc = dalloc(c, &p.llf, F)) != FASTFCA_OK) return rc;
-    if ((rc = dalloc(c, &p.Bh, F * M * M)) != FASTFCA_OK) return rc;
     return FASTFCA_OK;
 }
 
@@ -751,7 +746,7 @@ int fastfca_sync(fastfca_ctx *c) {
 int fastfca_loglik(fastfca_ctx *c, int b, double *ll_per_bin, double *ll_per_f) {
     if (!valid_problem(c, b)) return c ? set_err(c, FASTFCA_E_ARG, "bad mixture index %d", b) : FASTFCA_E_ARG;
     auto &p = c->probs[b];
-    hipError_t e = launch_pinv(p.items, p.F, p.M, nullptr, p.ldet, c->stream);
+    hipError_t e = launch_ldet(p.items, p.F, p.M, p.ldet, c->stream);
     if (e == hipSuccess) e = launch_loglik_terms(p.items, p.F, p.M, p.ldet, p.llf, c->stream);
     std::vector<double> llf(p.F);
     if (e == hipSuccess)
@@ -791,8 +786,7 @@ int fastfca_ll_trace(fastfca_ctx *c, int b, double *trace, int max_n) {
 int fastfca_mwf(fastfca_ctx *c, int b, fastfca_c64 *y) {
     if (!valid_problem(c, b) || !y) return c ? set_err(c, FASTFCA_E_ARG, "bad arguments") : FASTFCA_E_ARG;
     auto &p = c->probs[b];
-    HIPCHK(c, launch_pinv(p.items, p.F, p.M, p.Bh, p.ldet, c->stream));
-    HIPCHK(c, launch_mwf_bins(p.items, p.Bh, p.F, p.T * p.B, p.M, reinterpret_cast<float2 *>(y), c->stream));
+    HIPCHK(c, launch_mwf_bins(p.items, p.F, p.T * p.B, p.M, reinterpret_cast<float2 *>(y), c->stream));
     return FASTFCA_OK;
 }
 
