@@ -97,3 +97,36 @@ def test_targets_preserve_the_model_covariance():
             assert abs(np.trace(Rn).real - M) < 1e-12
             np.testing.assert_allclose(np.exp(tv[f, n]) * Rn[0, 0].real, v[f, :, n] * R[n][0, 0].real, rtol=1e-12)
             np.testing.assert_allclose(np.exp(tl[f, n]), np.real(np.diag(Rn)), rtol=1e-12)
+
+
+def test_adamw_two_steps_from_the_decoupled_definition():
+    """AdamW (Adam with decoupled weight decay): after k steps the first and
+    second moments are the bias-corrected exponential averages
+        m_k = (1 - b1) sum_{i<=k} b1^(k-i) g_i,   v_k = (1 - b2) sum_{i<=k} b2^(k-i) g_i^2,
+    and the parameter moves by lr * (m_k / (1 - b1^k) / (sqrt(v_k / (1 - b2^k)) + eps)
+    + wd * p_{k-1}), the decay acting on the parameter, not on the gradient.
+    Written here with the moments summed out in closed form for two steps;
+    a constant gradient makes the bias-corrected ratio exactly sign(g)."""
+    lr, b1, b2, eps, wd = 0.1, 0.9, 0.999, 1e-8, 0.01
+    # constant gradient: each step moves by lr * (1 + wd * p) (ratio exactly 1)
+    p, m, v = np.array([1.0]), np.zeros(1), np.zeros(1)
+    p1, m, v = net_ref.adamw(p, np.array([0.5]), m, v, lr, b1, b2, 0.0, wd, 1, 1.0)
+    p2, m, v = net_ref.adamw(p1, np.array([0.5]), m, v, lr, b1, b2, 0.0, wd, 2, 1.0)
+    np.testing.assert_allclose(p1, 1.0 - lr * (1.0 + wd * 1.0), rtol=1e-14)
+    np.testing.assert_allclose(p2, p1 - lr * (1.0 + wd * p1), rtol=1e-14)
+    # two different gradients, with a gradient scale of 0.5 applied first
+    g1, g2, gs = 0.8, -0.3, 0.5
+    p0 = np.array([2.0])
+    q1, m, v = net_ref.adamw(p0, np.array([g1]), np.zeros(1), np.zeros(1), lr, b1, b2, eps, wd, 1, gs)
+    q2, m, v = net_ref.adamw(q1, np.array([g2]), m, v, lr, b1, b2, eps, wd, 2, gs)
+    a1, a2 = gs * g1, gs * g2
+    m2 = (1 - b1) * (b1 * a1 + a2)
+    v2 = (1 - b2) * (b2 * a1 ** 2 + a2 ** 2)
+    step1 = a1 / (abs(a1) + eps)                       # m_1/(1-b1) = a1, v_1/(1-b2) = a1^2
+    step2 = (m2 / (1 - b1 ** 2)) / (np.sqrt(v2 / (1 - b2 ** 2)) + eps)
+    r1 = 2.0 - lr * (step1 + wd * 2.0)
+    r2 = r1 - lr * (step2 + wd * r1)
+    np.testing.assert_allclose(q1, r1, rtol=1e-14)
+    np.testing.assert_allclose(q2, r2, rtol=1e-13)
+    np.testing.assert_allclose(m, m2, rtol=1e-14)
+    np.testing.assert_allclose(v, v2, rtol=1e-14)
