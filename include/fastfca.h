@@ -59,7 +59,8 @@ enum {
     FASTFCA_E_SINGULAR = -4,    /* IP system (eq:ip1) numerically singular       */
     FASTFCA_E_NONFINITE = -5,   /* NaN/Inf in input or in an iterate             */
     FASTFCA_E_STATE = -6,       /* call not valid in the context's state         */
-    FASTFCA_E_UNSUPPORTED = -7  /* shape outside the compiled kernel families    */
+    FASTFCA_E_UNSUPPORTED = -7, /* shape outside the compiled kernel families    */
+    FASTFCA_E_DECREASE = -8     /* log-likelihood fell between two iterations   */
 };
 
 /* Shape limits of the compiled kernels: 2 <= M <= FASTFCA_MAX_M,
@@ -259,6 +260,17 @@ enum {
  */
 int fastfca_set_algorithm(fastfca_ctx *c, int algo);
 
+/*
+ * fastfca_set_ll_alarm -- tolerance of the likelihood alarm of later
+ * fastfca_em_step calls. Algorithms 1 and 2 never lower the log-likelihood
+ * (Sec. III-C, Sec. IV-E); a frequency whose recorded LL per bin falls by
+ * more than tol between two iterations of one call is stopped there with
+ * FASTFCA_E_DECREASE (reported, with the frequency, by the next
+ * synchronizing call), as a sign that the arithmetic has broken down.
+ * Default 1e-3; +INFINITY disables the alarm; NaN is E_ARG.
+ */
+int fastfca_set_ll_alarm(fastfca_ctx *c, double tol);
+
 /* Schedule of a batch context's fastfca_em_step. */
 enum {
     FASTFCA_SCHEDULE_CLASSES = 0,    /* one launch per (M, N, T-bucket) class, workgroups sized to T */
@@ -416,6 +428,54 @@ int fastfca_ws_targets(const fastfca_c128 *P, const float *lambda, const float *
  * lambda[f][n][m] = exp(ll[f][n][m]) (arguments clamped to [-60, 60]). */
 int fastfca_ws_apply(const float *lv, const float *ll, int F, int T, int M, int N, float *v, float *lambda,
                      void *stream);
+
+/*
+ * The trained warm-start network as fastfca_warmstart consumes it: the
+ * operands of fastfca_net_forward_fused plus the lambda head. Every pointer
+ * is a device pointer owned by the caller except Wb and b, HOST arrays of
+ * L + 1 device pointers.
+ *   M, N     microphones and sources (must match the mixture), N <= 8, M <= 4
+ *   C, L     channels (a multiple of 16 up to 64) and residual layers (<= 8)
+ *   Wb, b    packed BF16 kernel-5 weights and FP32 biases of layers 0..L
+ *   Kp0      row length of the packed layer-0 weights (16 or 32, >= 5 M)
+ *   Wv, ldv  FP32 head weights [N][ldv] (ldv >= C); bv its biases [N]
+ *   Wl, bl   FP32 lambda head [N*M][C] and biases [N*M]
+ */
+typedef struct {
+    int M, N, C, L;
+    const uint16_t *const *Wb;
+    const float *const *b;
+    int Kp0;
+    const float *Wv;
+    int ldv;
+    const float *bv;
+    const float *Wl;
+    const float *bl;
+} fastfca_net;
+
+/*
+ * fastfca_warmstart -- replace the current start of mixture b by a learned
+ * warm start, judged by the method itself (the paper names initialization
+ * and convergence acceleration as future work, Sec. VIII; the IP+EM
+ * iteration that follows is the refiner, the fallback and the judge):
+ *   1. P <- P0 = C_f^{-1/2} and the features (fastfca_ws_features);
+ *   2. net != NULL: the network (fastfca_net_forward_fused, the lambda head)
+ *      and lambda = exp(ll), v = exp(lv) (fastfca_ws_apply);
+ *      net == NULL: the whitening-only start lambda = 1,
+ *      v_tn = (1/(M N)) sum_m |(P0^H x_t)_m|^2;
+ *   3. judge, per frequency (every frequency is its own problem, Sec. II):
+ *      the new start is kept where its log-likelihood (eq:negll, double
+ *      precision, as fastfca_loglik) is finite and not below that of the
+ *      start it replaces; elsewhere that start is restored bit for bit.
+ * Frame-model contexts (fastfca_init, fastfca_init_batch) with M <= 4 only:
+ * E_STATE for block and FastMNMF contexts, E_ARG for a network whose shape
+ * does not match. Asynchronous on the context's stream unless n_taken
+ * (host, may be NULL) is given: then it synchronizes and stores the number
+ * of frequencies that kept the new start. Clears the mixture's recorded
+ * failure state. Allocates its workspace (features, activations, the saved
+ * start) on the first call for a mixture size and keeps it with the context.
+ */
+int fastfca_warmstart(fastfca_ctx *c, int b, const fastfca_net *net, int *n_taken);
 
 #ifdef __cplusplus
 }

@@ -416,6 +416,82 @@ hipError_t launch_seeded_init(const float2 *x, const float *z, float *lam, float
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ warm start
+// Whitening-only start: lambda = 1 and every source gets an equal share of
+// the whitened power, v_tn = (1/(M N)) sum_m |(P0^H x_t)_m|^2, with P0 the
+// whitening matrix already stored in P. One thread per frame.
+template <int M>
+__global__ void ws_whitened_kernel(const float2 *x, const double2 *P, float *lam, float *v, int T, int N) {
+    const int f = blockIdx.y;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float2 Pw[M * M];
+    if (threadIdx.x < M * M) {
+        const double2 a = P[static_cast<size_t>(f) * M * M + threadIdx.x];
+        Pw[threadIdx.x] = make_float2(static_cast<float>(a.x), static_cast<float>(a.y));
+    }
+    if (blockIdx.x == 0 && static_cast<int>(threadIdx.x) < N * M) lam[static_cast<size_t>(f) * N * M + threadIdx.x] = 1.0f;
+    __syncthreads();
+    if (t >= T) return;
+    const float2 *xt = x + (static_cast<size_t>(f) * T + t) * M;
+    float2 xv[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) xv[r] = xt[r];
+    float pw = 0.0f;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        float yr = 0.0f, yi = 0.0f;
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            const float2 a = Pw[r * M + m];
+            yr = fmaf(a.x, xv[r].x, fmaf(a.y, xv[r].y, yr));
+            yi = fmaf(a.x, xv[r].y, fmaf(-a.y, xv[r].x, yi));
+        }
+        pw = fmaf(yr, yr, fmaf(yi, yi, pw));
+    }
+    const float share = pw / static_cast<float>(M * N);
+    float *vt = v + (static_cast<size_t>(f) * T + t) * N;
+    for (int n = 0; n < N; ++n) vt[n] = share;
+}
+
+hipError_t launch_ws_whitened(const float2 *x, const double2 *P, float *lam, float *v, int F, int T, int M, int N,
+                              hipStream_t s) {
+    if (N * M > kAuxThreads) return hipErrorInvalidValue;
+    dim3 grid((T + kAuxThreads - 1) / kAuxThreads, F);
+#define FFCA_CALL(MM) hipLaunchKernelGGL(ws_whitened_kernel<MM>, grid, dim3(kAuxThreads), 0, s, x, P, lam, v, T, N)
+    FFCA_M_SWITCH(M, FFCA_CALL)
+#undef FFCA_CALL
+    return hipGetLastError();
+}
+
+// Judge of a warm start, per frequency (each frequency is its own problem):
+// the new start stays where its log-likelihood is finite and not below that
+// of the start it replaced; elsewhere the saved start is copied back. Counts
+// the frequencies that kept the new start. One workgroup per frequency.
+__global__ void ws_select_kernel(const double *ll_old, const double *ll_new, double2 *P, float *lam, float *v,
+                                 const double2 *P_old, const float *lam_old, const float *v_old, int T, int M,
+                                 int N, int *n_taken) {
+    const int f = blockIdx.x;
+    const double a = ll_old[f], b = ll_new[f];
+    const bool take = (b == b) && fabs(b) < INFINITY && b >= a;
+    if (take) {
+        if (threadIdx.x == 0) atomicAdd(n_taken, 1);
+        return;
+    }
+    const size_t fP = static_cast<size_t>(f) * M * M, fl = static_cast<size_t>(f) * N * M;
+    const size_t fv = static_cast<size_t>(f) * T * N;
+    for (int i = threadIdx.x; i < M * M; i += blockDim.x) P[fP + i] = P_old[fP + i];
+    for (int i = threadIdx.x; i < N * M; i += blockDim.x) lam[fl + i] = lam_old[fl + i];
+    for (int i = threadIdx.x; i < T * N; i += blockDim.x) v[fv + i] = v_old[fv + i];
+}
+
+hipError_t launch_ws_select(const double *ll_old, const double *ll_new, double2 *P, float *lam, float *v,
+                            const double2 *P_old, const float *lam_old, const float *v_old, int F, int T, int M,
+                            int N, int *n_taken, hipStream_t s) {
+    hipLaunchKernelGGL(ws_select_kernel, dim3(F), dim3(kAuxThreads), 0, s, ll_old, ll_new, P, lam, v, P_old,
+                       lam_old, v_old, T, M, N, n_taken);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ block covariances
 // Xhat_j = (1/B) sum_b x_{jB+b} x_{jB+b}^H (Sec. VI) as M^2 real parameters:
 // the diagonal, then re/im of the upper triangle in row-major order. One

@@ -106,15 +106,53 @@ __device__ __forceinline__ float wave_sum4_rows(float a, float b, float c, float
     return row_sum(__uint_as_float(q[0]) + __uint_as_float(q[1]));
 }
 
+// The same exchange for double precision values: both 32-bit halves of each
+// value move with the same lane permutation.
+__device__ __forceinline__ double join_d(unsigned int lo, unsigned int hi) {
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+__device__ __forceinline__ void permlane32_swap_d(double &x, double &y) {
+    const unsigned long long bx = static_cast<unsigned long long>(__double_as_longlong(x));
+    const unsigned long long by = static_cast<unsigned long long>(__double_as_longlong(y));
+    const auto lo = __builtin_amdgcn_permlane32_swap(static_cast<unsigned int>(bx), static_cast<unsigned int>(by),
+                                                     false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(static_cast<unsigned int>(bx >> 32),
+                                                     static_cast<unsigned int>(by >> 32), false, false);
+    x = join_d(lo[0], hi[0]);
+    y = join_d(lo[1], hi[1]);
+}
+__device__ __forceinline__ void permlane16_swap_d(double &x, double &y) {
+    const unsigned long long bx = static_cast<unsigned long long>(__double_as_longlong(x));
+    const unsigned long long by = static_cast<unsigned long long>(__double_as_longlong(y));
+    const auto lo = __builtin_amdgcn_permlane16_swap(static_cast<unsigned int>(bx), static_cast<unsigned int>(by),
+                                                     false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(static_cast<unsigned int>(bx >> 32),
+                                                     static_cast<unsigned int>(by >> 32), false, false);
+    x = join_d(lo[0], hi[0]);
+    y = join_d(lo[1], hi[1]);
+}
+// wave_sum4_rows with every cross-lane add in double precision.
+__device__ __forceinline__ double wave_sum4_rows(double a, double b, double c, double d) {
+    permlane32_swap_d(a, c);
+    permlane32_swap_d(b, d);
+    double sac = a + c;
+    double sbd = b + d;
+    permlane16_swap_d(sac, sbd);
+    return row_sum(sac + sbd);
+}
+
 // Wavefront sums of V values: value v ends in row v % 4 of out[v / 4]
-// (wave_sum4_rows on groups of four, zero-padded).
-template <int V>
-__device__ __forceinline__ void wave_sums_rows(const float (&x)[V], float (&out)[(V + 3) / 4]) {
+// (wave_sum4_rows on groups of four, zero-padded). With a double output the
+// single precision lane partials are promoted first and the whole
+// cross-lane tree runs in double precision.
+template <int V, class R>
+__device__ __forceinline__ void wave_sums_rows(const float (&x)[V], R (&out)[(V + 3) / 4]) {
 #pragma unroll
     for (int g = 0; g < (V + 3) / 4; ++g)
-        out[g] = wave_sum4_rows(x[4 * g], 4 * g + 1 < V ? x[4 * g + 1 < V ? 4 * g + 1 : 0] : 0.0f,
-                                4 * g + 2 < V ? x[4 * g + 2 < V ? 4 * g + 2 : 0] : 0.0f,
-                                4 * g + 3 < V ? x[4 * g + 3 < V ? 4 * g + 3 : 0] : 0.0f);
+        out[g] = wave_sum4_rows(static_cast<R>(x[4 * g]),
+                                static_cast<R>(4 * g + 1 < V ? x[4 * g + 1 < V ? 4 * g + 1 : 0] : 0.0f),
+                                static_cast<R>(4 * g + 2 < V ? x[4 * g + 2 < V ? 4 * g + 2 : 0] : 0.0f),
+                                static_cast<R>(4 * g + 3 < V ? x[4 * g + 3 < V ? 4 * g + 3 : 0] : 0.0f));
 }
 
 // Sum over the 64 lanes of a wavefront; the result is wave-uniform.

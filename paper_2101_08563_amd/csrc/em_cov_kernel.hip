@@ -12,7 +12,7 @@ __global__ void __launch_bounds__(kResidentBins / BPT) em_cov_kernel(EmLaunch a)
     __shared__ EmSmem<M * M * M, 2 * N * M, wave_slots(BPT)> sm;
     const WorkItem &it = a.items[blockIdx.x];
     if (*it.status != ST_OK) return;  // frozen after an earlier failure
-    em_item<M, N, BPT, true>(it, a.n_iter, a.algo, sm);
+    em_item<M, N, BPT, true>(it, a.n_iter, a.algo, a.ll_alarm, sm);
 }
 
 template <int M, int N>

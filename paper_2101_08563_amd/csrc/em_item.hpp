@@ -41,9 +41,9 @@ constexpr double kLnPi = 1.1447298858494002;  // ln(pi)
 // per wave of the largest workgroup it allows, at least 4.
 constexpr int wave_slots(int bpt) { return kResidentBins / bpt / 64 < 4 ? 4 : kResidentBins / bpt / 64; }
 
-// LDS of one workgroup. Phase A leaves one partial per wave of each of the
-// M^3 parameters of the Q_m in redq and one partial per 16-lane row (four per
-// wave) of the likelihood terms in red_d; each L reduction of phase C (M
+// LDS of one workgroup. Phase A leaves one double precision partial per wave
+// of each of the M^3 parameters of the Q_m in redq and one partial per 16-lane
+// row (four per wave) of the likelihood terms in red_d; each L reduction of phase C (M
 // values, or the 2NM sums of the multiplicative rule) one partial per wave in
 // redc, double buffered so that one barrier per reduction suffices. Slots of
 // waves that do not exist stay zero. RQ >= M^3, RC >= 2NM values; NWS wave
@@ -52,14 +52,14 @@ template <int RQ, int RC, int NWS>
 struct EmSmem {
     static constexpr int kRowSlots = 4 * NWS;
     static constexpr int kWaveSlots = NWS;
-    alignas(16) float redq[RQ][NWS];
+    alignas(16) double redq[RQ][NWS];
     alignas(16) double red_d[4 * NWS];
     alignas(16) float redc[2][RC][NWS];
     double qtot[RQ];
     double2 Pd[kMaxM * kMaxM];
     float2 P32[kMaxM * kMaxM];
     IpSmLds<kMaxM> ip;           // IP scratch (M = 3, 4)
-    double ldet[2];              // ln|det P|^2 of the IP of iterations of each parity
+    double ldet[2];              // ln|det P|^2 (|det P|^2 for M = 2) of the IP of iterations of each parity
     int flag;                    // IP status
     int flag_ll;                 // likelihood status
 };
@@ -162,6 +162,20 @@ __device__ __forceinline__ float sum_waves(const float *p, int nw) {
     }
     return tot;
 }
+template <int NS>
+__device__ __forceinline__ double sum_waves(const double *p, int nw) {
+    double tot = 0.0;
+#pragma unroll
+    for (int g = 0; g < NS / 4; ++g) {
+        if (g == 0 || g * 4 < nw) {
+            const double2 a = *reinterpret_cast<const double2 *>(p + 4 * g);
+            const double2 b = *reinterpret_cast<const double2 *>(p + 4 * g + 2);
+            const double u = (a.x + a.y) + (b.x + b.y);
+            tot = g == 0 ? u : tot + u;
+        }
+    }
+    return tot;
+}
 
 // IP sweep for M = 2 in registers (every lane of wave 0 computes the same
 // values). For 2 x 2 matrices the solve of eq:ip1, w = (P^H Q_m)^{-1} e_m,
@@ -191,9 +205,11 @@ __device__ __forceinline__ float sum_waves(const float *p, int nw) {
 // stored unless both columns pass.
 // P: the current P (row-major), read by the caller before the slot sums so
 // that both LDS reads are in flight together.
+// det2: |det P|^2 of the new P (its logarithm is left to the caller, off the
+// IP's critical path).
 template <class Smem>
 __device__ __forceinline__ int ip_sweep_reg2(Smem &sm, const cd (&P)[4], const double (&q)[8], double qscale,
-                                             double &ldet) {
+                                             double &det2) {
     const cd P00 = P[0], P01 = P[1], P10 = P[2], P11 = P[3];
     // the Q_m terms of both columns
     double dq[2], nq[2];
@@ -245,8 +261,7 @@ __device__ __forceinline__ int ip_sweep_reg2(Smem &sm, const cd (&P)[4], const d
     const int stat2 = !fin[1] ? ST_NONFINITE : (!pivot_ok(1, c2 * de2, np2, t2) ? ST_SINGULAR : ST_OK);
     stat = stat != ST_OK ? stat : stat2;
     if (stat != ST_OK) return stat;
-    // ln|det P|^2 for the likelihood trace (single precision logarithm)
-    ldet = static_cast<double>(ln_fast(static_cast<float>(abs2(W00 * W11 - W01 * W10))));
+    det2 = abs2(W00 * W11 - W01 * W10);
     sm.Pd[0] = st(W00);
     sm.Pd[1] = st(W01);
     sm.Pd[2] = st(W10);
@@ -263,7 +278,7 @@ __device__ __forceinline__ int ip_sweep_reg2(Smem &sm, const cd (&P)[4], const d
 // whose block covariance Xhat_j (M^2 real parameters, read from it.z) replaces
 // x_j x_j^H: Q_m takes Xhat_j / sigma^2 and U_mj = w_m^H Xhat_j w_m.
 template <int M, int N, int BPT, bool COV, class Smem>
-__device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo, Smem &sm) {
+__device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo, double alarm, Smem &sm) {
     constexpr int NQ = M * M * M;
     constexpr int M2 = M * M;
     const int tid = threadIdx.x;
@@ -328,13 +343,14 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
         sm.flag = ST_OK;
         sm.flag_ll = ST_OK;
     }
-    for (int i = tid; i < static_cast<int>(sizeof(sm.redq) / sizeof(float)); i += nthr) (&sm.redq[0][0])[i] = 0.0f;
+    for (int i = tid; i < static_cast<int>(sizeof(sm.redq) / sizeof(double)); i += nthr) (&sm.redq[0][0])[i] = 0.0;
     for (int i = tid; i < static_cast<int>(sizeof(sm.redc) / sizeof(float)); i += nthr) (&sm.redc[0][0][0])[i] = 0.0f;
     for (int i = tid; i < NR; i += nthr) sm.red_d[i] = 0.0;
     __syncthreads();
 
-    double ldet_prev = 0.0;  // ln|det P|^2 of the latest iterate (wave 0)
+    double ldet_prev = M == 2 ? 1.0 : 0.0;  // ln|det P|^2 (M = 2: |det P|^2) of the latest iterate (wave 0)
     double *const ll_trace = it.ll_trace;
+    double ll_last = 0.0;  // LL of the previous iterate (likelihood wave)
     int buf = 0;
     int status = ST_OK;
 
@@ -407,10 +423,14 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
             }
         }
         // wave partials of Q (four values per reduction, value 4g + r in row
-        // r) and row partials of the LL terms to LDS
+        // r) and row partials of the LL terms to LDS. Each lane's partial
+        // (BPT bins) is single precision; every sum across lanes and waves is
+        // double precision: with the single precision tree the rounding of
+        // the Q_m, amplified by an ill-conditioned IP system, moved the
+        // likelihood by more than 1e-6 nats per bin within ten iterations.
         if (!last) {
             constexpr int NGQ = (NQ + 3) / 4;
-            float tq[NGQ];
+            double tq[NGQ];
             wave_sums_rows<NQ>(q, tq);
             if ((lane & 15) == 0) {
 #pragma unroll
@@ -424,11 +444,18 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
         if (wid == llw && iter > 0) {
             // eq:negll for the previous iterate, beside the IP on wave 0
             const double s = sum_rows<NR>(sm.red_d, nw);
-            const double ll = sm.ldet[(iter - 1) & 1] - static_cast<double>(M) * kLnPi - s * invT;
+            // M = 2: the IP wave left |det P|^2; its logarithm in double
+            // precision is taken here, beside the IP of the next iterate
+            const double ldp = sm.ldet[(iter - 1) & 1];
+            const double ll = (M == 2 ? log(ldp) : ldp) - static_cast<double>(M) * kLnPi - s * invT;
             if (lane == 0) {
                 ll_trace[iter - 1] = ll;
-                if (!(ll == ll) || ll == INFINITY || ll == -INFINITY) sm.flag_ll = ST_NONFINITE;
+                if (!(ll == ll) || ll == INFINITY || ll == -INFINITY)
+                    sm.flag_ll = ST_NONFINITE;
+                else if (iter > 1 && ll < ll_last - alarm)  // Algorithms 1 and 2 never lower it
+                    sm.flag_ll = ST_DECREASE;
             }
+            ll_last = ll;
         }
         if (wid == 0 && !last) {
             double ldet = 0.0;
@@ -437,12 +464,12 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                 // reads the eight sums of lanes 0-7 from registers
                 const cd Pc[4] = {ld(sm.Pd[0]), ld(sm.Pd[1]), ld(sm.Pd[2]), ld(sm.Pd[3])};
                 double qs[8];
-                const float mine = sum_waves<NW>(sm.redq[lane & 7], nw);
+                const double mine = sum_waves<NW>(sm.redq[lane & 7], nw);
 #pragma unroll
-                for (int i = 0; i < 8; ++i) qs[i] = static_cast<double>(readlane_f(mine, i));
+                for (int i = 0; i < 8; ++i) qs[i] = readlane_d(mine, i);
                 status = ip_sweep_reg2(sm, Pc, qs, sqrtT, ldet);
             } else {
-                if (lane < NQ) sm.qtot[lane] = static_cast<double>(sum_waves<NW>(sm.redq[lane], nw)) * invT;
+                if (lane < NQ) sm.qtot[lane] = sum_waves<NW>(sm.redq[lane], nw) * invT;
                 __threadfence_block();
                 __builtin_amdgcn_wave_barrier();
                 // IP sweep in double precision through the inverses
@@ -691,7 +718,7 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
     if (wid == 0) {
         if (lane < M * M) it.P[lane] = sm.Pd[lane];
         if (lane == 0) {
-            *it.ldet = ldet_prev;
+            *it.ldet = (M == 2) ? log(ldet_prev) : ldet_prev;
             if (status != ST_OK) *it.status = status;
         }
     }

@@ -16,7 +16,7 @@ __global__ void __launch_bounds__(kResidentBins / BPT)
     __shared__ EmSmem<M * M * M, 2 * N * M, wave_slots(BPT)> sm;
     const WorkItem &it = a.items[blockIdx.x];
     if (*it.status != ST_OK) return;  // frozen after an earlier failure
-    em_item<M, N, BPT, false>(it, a.n_iter, a.algo, sm);
+    em_item<M, N, BPT, false>(it, a.n_iter, a.algo, a.ll_alarm, sm);
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(kResidentBins / BPT) em_persistent_kernel(EmLa
         if (*it.status != ST_OK) continue;
         switch (it.M * 16 + it.N) {
 #define FFCA_CASE(MM, NN) \
-    case MM * 16 + NN: em_item<MM, NN, BPT, false>(it, a.n_iter, a.algo, sm); break;
+    case MM * 16 + NN: em_item<MM, NN, BPT, false>(it, a.n_iter, a.algo, a.ll_alarm, sm); break;
             FFCA_PERSISTENT_CLASSES(FFCA_CASE)
 #undef FFCA_CASE
             default: break;

@@ -53,7 +53,7 @@ struct WideSmem {
 };
 
 template <int M, int N, int BPT>
-__device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, WideSmem &sm) {
+__device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, double alarm, WideSmem &sm) {
     constexpr int M2 = M * M;
     constexpr int G = 64 / M2;  // lane groups in the weighted-covariance pass
     const int tid = threadIdx.x;
@@ -105,6 +105,7 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, Wid
     float *ws = stg + 64 * M * 2;                  // [64][M]
 
     double ldet_prev = 0.0;
+    double ll_last = 0.0;  // LL of the previous iterate (wave 0)
     double llp = 0.0;  // LL terms of the latest iterate (end of phase C)
     int buf = 0;
     int status = ST_OK;
@@ -181,7 +182,11 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, Wid
                 for (int w = 0; w < kWideWaves; ++w) s += sm.red_d[buf][w];
                 const double ll = ldet_prev - static_cast<double>(M) * kWideLnPi - s * invT;
                 if (lane == 0) it.ll_trace[iter - 1] = ll;
-                if (!(ll == ll) || ll == INFINITY || ll == -INFINITY) status = ST_NONFINITE;
+                if (!(ll == ll) || ll == INFINITY || ll == -INFINITY)
+                    status = ST_NONFINITE;
+                else if (iter > 1 && ll < ll_last - alarm)  // Algorithm 1 never lowers it
+                    status = ST_DECREASE;
+                ll_last = ll;
             }
             if (!last && status == ST_OK) {
                 double ldet = 0.0;

@@ -14,7 +14,7 @@ __global__ void __launch_bounds__(kWideBins / BPT) em_wide_kernel(EmLaunch a) {
     __shared__ WideSmem sm;
     const WorkItem &it = a.items[blockIdx.x];
     if (*it.status != ST_OK) return;
-    em_wide_item<M, N, BPT>(it, a.n_iter, sm);
+    em_wide_item<M, N, BPT>(it, a.n_iter, a.ll_alarm, sm);
 }
 
 using WideFn = void (*)(EmLaunch);

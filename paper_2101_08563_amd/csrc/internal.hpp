@@ -27,7 +27,7 @@ struct WorkItem {
 };
 
 // Status codes written by kernels (mirror the public ABI values).
-enum : int { ST_OK = 0, ST_SINGULAR = -4, ST_NONFINITE = -5 };
+enum : int { ST_OK = 0, ST_SINGULAR = -4, ST_NONFINITE = -5, ST_DECREASE = -8 };
 
 // Largest T handled by the resident IP+EM kernels: a workgroup holds at most
 // kResidentBins bins (threads * bins-per-thread), with threads <= 2048 / BPT.
@@ -46,6 +46,8 @@ struct EmLaunch {
     int n_iter;
     int *queue;             // persistent launch: next-item counter (nullptr otherwise)
     int algo;               // kAlgoEM or kAlgoMM
+    double ll_alarm;        // a frequency whose LL per bin falls by more than this between two
+                            // iterations of a call is stopped with ST_DECREASE (+inf: never)
 };
 
 // Launch one EM kernel (Algorithm 1 for n_iter iterations) over `n_items`

@@ -29,7 +29,7 @@ namespace ffca {
 template <int M, int N, int NWS>
 struct MnmfSmem {
     static constexpr int RC = 2 * kMnmfKC * N > 2 * N * M ? 2 * kMnmfKC * N : 2 * N * M;
-    alignas(16) float redq[M * M * M][4 * NWS];
+    alignas(16) double redq[M * M * M][4 * NWS];  // row partials of the Q_m, double precision
     alignas(16) double red_d[4 * NWS];
     alignas(16) float redc[2][RC][NWS];
     float sums[RC];
@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(kResidentBins / BPT) mnmf_freq_kernel(MnmfLaun
         sm.Pd[tid] = p;
         sm.P32[tid] = make_float2(static_cast<float>(p.x), static_cast<float>(p.y));
     }
-    for (int q = tid; q < static_cast<int>(sizeof(sm.redq) / sizeof(float)); q += nthr) (&sm.redq[0][0])[q] = 0.0f;
+    for (int q = tid; q < static_cast<int>(sizeof(sm.redq) / sizeof(double)); q += nthr) (&sm.redq[0][0])[q] = 0.0;
     for (int q = tid; q < static_cast<int>(sizeof(sm.redc) / sizeof(float)); q += nthr) (&sm.redc[0][0][0])[q] = 0.0f;
     for (int q = tid; q < NR; q += nthr) sm.red_d[q] = 0.0;
     if (tid == 0) sm.flag = ST_OK;
@@ -203,11 +203,14 @@ __global__ void __launch_bounds__(kResidentBins / BPT) mnmf_freq_kernel(MnmfLaun
                 for (int e = 0; e < M * M; ++e) q[m * M * M + e] = fmaf(w, z[e], q[m * M * M + e]);
             }
         }
+        // lane partials are single precision; the sums across lanes and waves
+        // are double precision (as in the frame model's kernel)
+        double qd[NQ];
 #pragma unroll
-        for (int e = 0; e < NQ; ++e) q[e] = row_sum(q[e]);
+        for (int e = 0; e < NQ; ++e) qd[e] = row_sum(static_cast<double>(q[e]));
         if (row_lead) {
 #pragma unroll
-            for (int e = 0; e < NQ; ++e) sm.redq[e][row_slot] = q[e];
+            for (int e = 0; e < NQ; ++e) sm.redq[e][row_slot] = qd[e];
         }
     }
     __syncthreads();
@@ -217,12 +220,14 @@ __global__ void __launch_bounds__(kResidentBins / BPT) mnmf_freq_kernel(MnmfLaun
         if constexpr (M == 2) {
             const cd Pc[4] = {ld(sm.Pd[0]), ld(sm.Pd[1]), ld(sm.Pd[2]), ld(sm.Pd[3])};
             double qs[8];
-            const float mine = sum_slots<NR>(sm.redq[lane & 7]);
+            const double mine = sum_slots<NR>(sm.redq[lane & 7]);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) qs[e] = static_cast<double>(readlane_f(mine, e));
-            st = ip_sweep_reg2(sm, Pc, qs, sqrt(static_cast<double>(T)), ldet);
+            for (int e = 0; e < 8; ++e) qs[e] = readlane_d(mine, e);
+            double det2 = 1.0;
+            st = ip_sweep_reg2(sm, Pc, qs, sqrt(static_cast<double>(T)), det2);
+            ldet = log(det2);
         } else {
-            if (lane < NQ) sm.qtot[lane] = static_cast<double>(sum_slots<NR>(sm.redq[lane])) * invT;
+            if (lane < NQ) sm.qtot[lane] = sum_slots<NR>(sm.redq[lane]) * invT;
             __threadfence_block();
             __builtin_amdgcn_wave_barrier();
             st = ip_sm<M, kMaxM>(sm.qtot, sm.Pd, sm.P32, sm.ip, ldet);

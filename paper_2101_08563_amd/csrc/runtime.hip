@@ -25,6 +25,19 @@ hipError_t launch_loglik_terms(const WorkItem *items, int n_items, int M, const 
 hipError_t launch_mwf_bins(const WorkItem *items, int F, int T, int M, float2 *y, hipStream_t s);
 hipError_t launch_synth(float2 *x, int F, int T, int M, int N, int K, float delta, uint64_t seed,
                         float *W, float2 *C, hipStream_t s);
+hipError_t launch_ws_whitened(const float2 *x, const double2 *P, float *lam, float *v, int F, int T, int M, int N,
+                              hipStream_t s);
+hipError_t launch_ws_select(const double *ll_old, const double *ll_new, double2 *P, float *lam, float *v,
+                            const double2 *P_old, const float *lam_old, const float *v_old, int F, int T, int M,
+                            int N, int *n_taken, hipStream_t s);
+hipError_t net_features(const float2 *x, int F, int T, int M, float eps, double2 *P0, float *feat, hipStream_t s);
+hipError_t net_forward_fused(const float *feat, int S, int M, int T, int C, int L, int N,
+                             const uint16_t *const *Wb, const float *const *b, int Kp0, const float *Wv, int ldv,
+                             const float *bv, float *lv, float *part, float *pooled, hipStream_t s);
+hipError_t net_linear_fwd(const float *in, int S, int C, const float *Wl, const float *bl, int J, float *out,
+                          hipStream_t s);
+hipError_t net_apply_outputs(const float *lv, const float *ll, int F, int T, int M, int N, float *v, float *lam,
+                             hipStream_t s);
 }  // namespace ffca
 
 using namespace ffca;
@@ -57,6 +70,27 @@ struct ClassCfg {
     std::vector<int> items;  // item indices of this class, in launch order
 };
 
+// Workspace of fastfca_warmstart, sized for the largest mixture seen. Each
+// buffer has its capacity in elements beside it.
+template <typename T>
+struct WsBuf {
+    T *p = nullptr;
+    size_t cap = 0;
+};
+struct WsScratch {
+    WsBuf<float> feat;      // [F][M][T] features
+    WsBuf<float> lv;        // [F][N][T] network log v
+    WsBuf<float> part;      // fused forward's per-tile sums
+    WsBuf<float> pooled;    // [F][C]
+    WsBuf<float> ll;        // [F][N*M] network log lambda
+    WsBuf<double2> P_old;   // the start being replaced
+    WsBuf<float> lam_old;
+    WsBuf<float> v_old;
+    WsBuf<double> ll_old;   // [F] per-frequency LL of the replaced start
+    WsBuf<double> ll_new;   // [F] per-frequency LL of the new start
+    WsBuf<int> taken;       // frequencies that kept the new start
+};
+
 // FastMNMF state (fastfca_mnmf_init): NMF factors and the V-rule scratch.
 struct MnmfState {
     int K = 0, threads = 0, bpt = 0;
@@ -68,6 +102,11 @@ struct MnmfState {
 };
 
 }  // namespace
+
+// Default tolerance of the likelihood alarm (nats per bin, per frequency,
+// between two iterations of one call): far above the single precision
+// noise of the per-iteration trace, far below any real decrease.
+constexpr double kDefaultLLAlarm = 1e-3;
 
 struct fastfca_ctx {
     int device = 0;
@@ -95,7 +134,9 @@ struct fastfca_ctx {
     hipGraphExec_t graph_exec = nullptr;
     int graph_n_iter = -1;
     int algo = kAlgoEM;
+    double ll_alarm = kDefaultLLAlarm;  // fastfca_set_ll_alarm
     MnmfState *mn = nullptr;          // FastMNMF context
+    WsScratch ws;                     // fastfca_warmstart workspace
     std::string err;
     char arch[64] = {0};
 };
@@ -133,6 +174,18 @@ int dalloc(fastfca_ctx *c, T **p, size_t count) {
                        hipGetErrorString(e));
     }
     return FASTFCA_OK;
+}
+
+// (Re)allocate one workspace buffer to hold at least n elements.
+template <typename T>
+int ws_reserve(fastfca_ctx *c, WsBuf<T> &b, size_t n) {
+    if (n <= b.cap && b.p) return FASTFCA_OK;
+    hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    int rc = dalloc(c, &b.p, n);
+    if (rc == FASTFCA_OK) b.cap = n;
+    return rc;
 }
 
 void free_problem(Problem &p) {
@@ -521,7 +574,7 @@ int record_em(fastfca_ctx *c, int n_iter) {
     if (c->mn) return record_mnmf(c, n_iter);
     if (c->persistent) {
         HIPCHK(c, launch_fill_int(c->d_queue, 1, 0, c->stream));
-        EmLaunch a{c->d_items, static_cast<int>(c->h_items.size()), n_iter, c->d_queue, c->algo};
+        EmLaunch a{c->d_items, static_cast<int>(c->h_items.size()), n_iter, c->d_queue, c->algo, c->ll_alarm};
         HIPCHK(c, launch_em_persistent(a, c->p_threads, c->p_bpt, c->p_grid, c->stream));
         return FASTFCA_OK;
     }
@@ -545,7 +598,7 @@ int record_em(fastfca_ctx *c, int n_iter) {
         const auto &cc = c->classes[k];
         hipStream_t st = (r % nstreams) == 0 ? c->stream : c->side[(r % nstreams) - 1];
         EmLaunch a{c->d_items + c->class_first[k], static_cast<int>(cc.items.size()), n_iter,
-                   nullptr, c->algo};
+                   nullptr, c->algo, c->ll_alarm};
         if (cc.wide)
             HIPCHK(c, launch_em_wide(cc.M, cc.N, cc.bpt, cc.threads, a,
                                      static_cast<int>(cc.items.size()), st));
@@ -578,8 +631,9 @@ int check_status(fastfca_ctx *c) {
             const int s = st[p.item0 + f];
             if (s != ST_OK)
                 return set_err(c, s, "mixture %zu frequency %d: %s", b, f,
-                               s == ST_SINGULAR ? "IP system numerically singular"
-                                                : "non-finite value in an iterate");
+                               s == ST_SINGULAR   ? "IP system numerically singular"
+                               : s == ST_DECREASE ? "log-likelihood decreased between two iterations"
+                                                  : "non-finite value in an iterate");
         }
     }
     return FASTFCA_OK;
@@ -867,6 +921,14 @@ int fastfca_set_config(fastfca_ctx *c, int threads, int bins_per_thread) {
     return FASTFCA_OK;
 }
 
+int fastfca_set_ll_alarm(fastfca_ctx *c, double tol) {
+    if (!c) return FASTFCA_E_ARG;
+    if (tol != tol) return set_err(c, FASTFCA_E_ARG, "ll alarm tolerance is NaN");
+    if (tol != c->ll_alarm) drop_graph(c);
+    c->ll_alarm = tol;
+    return FASTFCA_OK;
+}
+
 int fastfca_set_algorithm(fastfca_ctx *c, int algo) {
     if (!c) return FASTFCA_E_ARG;
     if (algo != FASTFCA_ALGO_EM && algo != FASTFCA_ALGO_MM)
@@ -1119,11 +1181,85 @@ void fastfca_destroy(fastfca_ctx *c) {
         hipFree(c->mn->vflag);
         delete c->mn;
     }
+    hipFree(c->ws.feat.p);
+    hipFree(c->ws.lv.p);
+    hipFree(c->ws.part.p);
+    hipFree(c->ws.pooled.p);
+    hipFree(c->ws.ll.p);
+    hipFree(c->ws.P_old.p);
+    hipFree(c->ws.lam_old.p);
+    hipFree(c->ws.v_old.p);
+    hipFree(c->ws.ll_old.p);
+    hipFree(c->ws.ll_new.p);
+    hipFree(c->ws.taken.p);
     hipFree(c->d_items);
     hipFree(c->d_status);
     hipFree(c->d_trace);
     hipFree(c->d_queue);
     delete c;
+}
+
+int fastfca_warmstart(fastfca_ctx *c, int b, const fastfca_net *net, int *n_taken) {
+    if (!valid_problem(c, b)) return c ? set_err(c, FASTFCA_E_ARG, "bad mixture index %d", b) : FASTFCA_E_ARG;
+    auto &p = c->probs[b];
+    if (p.blocks || c->mn) return set_err(c, FASTFCA_E_STATE, "warm start: frame-model contexts only");
+    if (p.M > 4) return set_err(c, FASTFCA_E_ARG, "warm start: M = %d > 4", p.M);
+    if (net) {
+        if (net->M != p.M || net->N != p.N)
+            return set_err(c, FASTFCA_E_ARG, "warm start: network for M=%d N=%d, mixture %d has M=%d N=%d", net->M,
+                           net->N, b, p.M, p.N);
+        if (net->C < 16 || net->C > 64 || net->C % 16 || net->L < 0 || net->L > 8 || net->N > 8 || !net->Wb ||
+            !net->b || !net->Wv || !net->bv || !net->Wl || !net->bl || net->ldv < net->C ||
+            (net->Kp0 != 16 && net->Kp0 != 32) || net->Kp0 < 5 * net->M)
+            return set_err(c, FASTFCA_E_ARG, "warm start: unsupported network (C=%d L=%d Kp0=%d)", net->C, net->L,
+                           net->Kp0);
+        for (int l = 0; l <= net->L; ++l)
+            if (!net->Wb[l] || !net->b[l]) return set_err(c, FASTFCA_E_ARG, "warm start: layer %d missing", l);
+    }
+    const size_t F = p.F, T = p.T, M = p.M, N = p.N;
+    auto &w = c->ws;
+    int rc = FASTFCA_OK;
+    if ((rc = ws_reserve(c, w.feat, F * M * T)) != FASTFCA_OK || (rc = ws_reserve(c, w.P_old, F * M * M)) != FASTFCA_OK ||
+        (rc = ws_reserve(c, w.lam_old, F * N * M)) != FASTFCA_OK || (rc = ws_reserve(c, w.v_old, F * T * N)) != FASTFCA_OK ||
+        (rc = ws_reserve(c, w.ll_old, F)) != FASTFCA_OK || (rc = ws_reserve(c, w.ll_new, F)) != FASTFCA_OK ||
+        (rc = ws_reserve(c, w.taken, 1)) != FASTFCA_OK)
+        return rc;
+    if (net && ((rc = ws_reserve(c, w.lv, F * N * T)) != FASTFCA_OK ||
+                (rc = ws_reserve(c, w.part, F * ((T + 63) / 64) * net->C)) != FASTFCA_OK ||
+                (rc = ws_reserve(c, w.pooled, F * net->C)) != FASTFCA_OK || (rc = ws_reserve(c, w.ll, F * N * M)) != FASTFCA_OK))
+        return rc;
+    hipStream_t s = c->stream;
+    // the start being replaced and its likelihood per frequency
+    HIPCHK(c, hipMemcpyAsync(w.P_old.p, p.P, sizeof(double2) * F * M * M, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(w.lam_old.p, p.lam, sizeof(float) * F * N * M, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(w.v_old.p, p.v, sizeof(float) * F * T * N, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, launch_ldet(p.items, p.F, p.M, p.ldet, s));
+    HIPCHK(c, launch_loglik_terms(p.items, p.F, p.M, p.ldet, w.ll_old.p, s));
+    // whitening P0 = C_f^{-1/2}, written as the new P, and the features
+    HIPCHK(c, net_features(p.x, p.F, p.T, p.M, 1e-8f, p.P, w.feat.p, s));
+    if (net) {
+        HIPCHK(c, net_forward_fused(w.feat.p, p.F, p.M, p.T, net->C, net->L, p.N, net->Wb, net->b, net->Kp0, net->Wv,
+                                    net->ldv, net->bv, w.lv.p, w.part.p, w.pooled.p, s));
+        HIPCHK(c, net_linear_fwd(w.pooled.p, p.F, net->C, net->Wl, net->bl, p.N * p.M, w.ll.p, s));
+        HIPCHK(c, net_apply_outputs(w.lv.p, w.ll.p, p.F, p.T, p.M, p.N, p.v, p.lam, s));
+    } else {
+        HIPCHK(c, launch_ws_whitened(p.x, p.P, p.lam, p.v, p.F, p.T, p.M, p.N, s));
+    }
+    // judge: the new start's likelihood against the old one's, per frequency
+    HIPCHK(c, launch_ldet(p.items, p.F, p.M, p.ldet, s));
+    HIPCHK(c, launch_loglik_terms(p.items, p.F, p.M, p.ldet, w.ll_new.p, s));
+    HIPCHK(c, launch_fill_int(w.taken.p, 1, 0, s));
+    HIPCHK(c, launch_ws_select(w.ll_old.p, w.ll_new.p, p.P, p.lam, p.v, w.P_old.p, w.lam_old.p, w.v_old.p, p.F, p.T, p.M,
+                               p.N, w.taken.p, s));
+    // the likelihood kernels record a singular P of a rejected start
+    HIPCHK(c, launch_fill_int(c->d_status + p.item0, p.F, ST_OK, s));
+    if (n_taken) {
+        int h = 0;
+        HIPCHK(c, hipMemcpyAsync(&h, w.taken.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        *n_taken = h;
+    }
+    return FASTFCA_OK;
 }
 
 }  // extern "C"

@@ -16,9 +16,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfastfca.so")
 
 OK = 0
-E_ARG, E_NOMEM, E_HIP, E_SINGULAR, E_NONFINITE, E_STATE, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6, -7
+E_ARG, E_NOMEM, E_HIP, E_SINGULAR, E_NONFINITE, E_STATE, E_UNSUPPORTED, E_DECREASE = -1, -2, -3, -4, -5, -6, -7, -8
 _NAMES = {E_ARG: "E_ARG", E_NOMEM: "E_NOMEM", E_HIP: "E_HIP", E_SINGULAR: "E_SINGULAR",
-          E_NONFINITE: "E_NONFINITE", E_STATE: "E_STATE", E_UNSUPPORTED: "E_UNSUPPORTED"}
+          E_NONFINITE: "E_NONFINITE", E_STATE: "E_STATE", E_UNSUPPORTED: "E_UNSUPPORTED", E_DECREASE: "E_DECREASE"}
 
 # Every entry point of include/fastfca.h with its ctypes signature.
 _vp, _i, _u64, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_double
@@ -39,6 +39,7 @@ SIGNATURES = {
     "fastfca_autotune": (_i, [_vp, _i, ctypes.c_char_p]),
     "fastfca_get_config": (_i, [_vp, _i, _pi, _pi]),
     "fastfca_set_algorithm": (_i, [_vp, _i]),
+    "fastfca_set_ll_alarm": (_i, [_vp, _d]),
     "fastfca_set_schedule": (_i, [_vp, _i]),
     "fastfca_init_blocks": (_i, [ctypes.POINTER(_vp), _vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _u64, _vp]),
     "fastfca_block_length": (_i, [_vp, _i]),
@@ -66,6 +67,7 @@ SIGNATURES = {
     "fastfca_ws_features": (_i, [_vp, _i, _i, _i, ctypes.c_float, _vp, _vp, _vp]),
     "fastfca_ws_targets": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _vp, _vp, _vp]),
     "fastfca_ws_apply": (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _vp, _vp]),
+    "fastfca_warmstart": (_i, [_vp, _i, _vp, _pi]),
 }
 
 
@@ -73,6 +75,12 @@ class Problem(ctypes.Structure):
     """fastfca_problem (one mixture of a batch)."""
     _fields_ = [("x", _vp), ("F", _i), ("T", _i), ("M", _i), ("N", _i),
                 ("P0", _vp), ("lambda0", _vp), ("v0", _vp)]
+
+
+class NetDesc(ctypes.Structure):
+    """fastfca_net (the trained warm-start network as fastfca_warmstart reads it)."""
+    _fields_ = [("M", _i), ("N", _i), ("C", _i), ("L", _i), ("Wb", _vp), ("b", _vp), ("Kp0", _i),
+                ("Wv", _vp), ("ldv", _i), ("bv", _vp), ("Wl", _vp), ("bl", _vp)]
 
 
 class FastFCAError(RuntimeError):
@@ -299,6 +307,22 @@ class FastFCA:
         _check_dev(lam, torch.float32, (F, N, M), "lam")
         _check_dev(v, torch.float32, (F, T, N), "v")
         self._chk(self._lib.fastfca_set_params(self._ctx, b, _ptr(P), _ptr(lam), _ptr(v)))
+
+    def warmstart(self, net=None, b=0, count=False):
+        """fastfca_warmstart: replace mixture b's start by the network's warm
+        start (net: a warmstart.ConvNet) or, with net=None, by the
+        whitening-only start; the library keeps the new start only in the
+        frequencies where its log-likelihood is not below the old one's.
+        count=True synchronizes and returns how many frequencies kept it."""
+        desc = net.descriptor() if net is not None else None
+        n = ctypes.c_int(0)
+        self._chk(self._lib.fastfca_warmstart(self._ctx, b, ctypes.byref(desc) if desc is not None else None,
+                                              ctypes.byref(n) if count else None))
+        return n.value if count else None
+
+    def set_ll_alarm(self, tol):
+        """fastfca_set_ll_alarm (float('inf') disables the alarm)."""
+        self._chk(self._lib.fastfca_set_ll_alarm(self._ctx, float(tol)))
 
     def set_config(self, threads=0, bins_per_thread=0):
         self._chk(self._lib.fastfca_set_config(self._ctx, int(threads), int(bins_per_thread)))

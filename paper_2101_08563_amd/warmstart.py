@@ -20,7 +20,7 @@ import time
 import numpy as np
 import torch
 
-from .fastfca import FastFCA, FastFCAError, _ptr, _stream, load_library, synth_mixture
+from .fastfca import FastFCA, FastFCAError, NetDesc, _ptr, _stream, load_library, synth_mixture
 
 
 def _kp(n):
@@ -140,6 +140,19 @@ class ConvNet:
         if keep:
             self._cache = (feat, hs, pres, pooled)
         return lv, ll
+
+    def descriptor(self):
+        """The fastfca_net descriptor of this network (for fastfca_warmstart);
+        the host pointer arrays live as long as the network."""
+        L = self.L
+        self._wb_arr = (ctypes.c_void_p * (L + 1))(*[self.Wb[i].data_ptr() for i in range(L + 1)])
+        self._b_arr = (ctypes.c_void_p * (L + 1))(*[self.b[i].data_ptr() for i in range(L + 1)])
+        wv = self.W[L + 1]
+        return NetDesc(M=self.M, N=self.N, C=self.C, L=L,
+                       Wb=ctypes.cast(self._wb_arr, ctypes.c_void_p).value,
+                       b=ctypes.cast(self._b_arr, ctypes.c_void_p).value, Kp0=_kp(self.M * 5),
+                       Wv=wv.data_ptr(), ldv=wv.shape[1], bv=self.b[L + 1].data_ptr(),
+                       Wl=self.Wl.data_ptr(), bl=self.bl.data_ptr())
 
     def fused_ok(self):
         """Shapes the one-launch inference kernel takes."""

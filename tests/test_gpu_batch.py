@@ -6,14 +6,11 @@ import torch
 
 import oracle
 from paper_2101_08563_amd import FastFCA, synth
+from parity_metrics import rel, report
 
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-
-
-def rel(a, b):
-    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
 
 
 def batch_inputs(n_mix=8, F=12, seed=0):
@@ -44,26 +41,38 @@ def test_batch_shapes_cover_the_classes():
     assert 200 <= min(Ts) and max(Ts) <= 2000
 
 
+@pytest.fixture(scope="module")
+def batch513():
+    """Eight mixtures of the batch workload's shapes at its F = 513
+    (T ~ U{200..2000}, M in {2, 3, 4}, N in {M+1, M+2}) with the oracle's fits."""
+    inputs = batch_inputs(8, F=513)
+    fits = []
+    for x, P0, lam0, v0, N in inputs:
+        Po, lo, vo, tro = oracle.fit(x, P0, lam0, v0, 20, trace=True)
+        llo, _ = oracle.loglik(x, Po, lo, vo)
+        fits.append((Po, lo, vo, tro, llo, oracle.mwf(x, Po, lo, vo)))
+    return inputs, fits
+
+
 @pytest.mark.parametrize("schedule", ["persistent", "classes"])
-def test_batch_matches_oracle_per_mixture(schedule):
-    inputs = batch_inputs(8, F=12)
+def test_batch_matches_oracle_per_mixture(schedule, batch513):
+    inputs, fits = batch513
     ctx, _ = make_batch(inputs)
     ctx.set_schedule(schedule)
     assert ctx.num_problems == 8
     ctx.em_step(20)
     ctx.sync()
-    for b, (x, P0, lam0, v0, N) in enumerate(inputs):
+    for b, ((x, P0, lam0, v0, N), (Po, lo, vo, tro, llo, yo)) in enumerate(zip(inputs, fits)):
         P, lam, v = (t.cpu().numpy() for t in ctx.get_params(b))
-        Po, lo, vo, tro = oracle.fit(x, P0, lam0, v0, 20, trace=True)
-        llo, _ = oracle.loglik(x, Po, lo, vo)
-        errs = dict(v=rel(v, vo), lam=rel(lam, lo), P=rel(P, Po), ll=abs(ctx.loglik(b) - llo))
-        print(schedule, "mixture", b, x.shape, N, errs, flush=True)
-        assert errs["v"] < 1e-4 and errs["lam"] < 1e-4 and errs["P"] < 1e-4 and errs["ll"] < 1e-6, errs
+        y = ctx.mwf(b).cpu().numpy()
+        errs = report(dict(P=P, lam=lam, v=v, y=y), Po, lo, vo, yo)
+        errs["ll"] = abs(ctx.loglik(b) - llo)
+        print(schedule, "mixture", b, x.shape, N, {k: "%.2e" % e for k, e in errs.items()}, flush=True)
+        for k in ("v", "lam", "P", "y", "v_f", "lam_f", "P_f", "y_f"):
+            assert errs[k] < 1e-4, (k, errs)
+        assert errs["v_log999"] < 1e-3 and errs["ll"] < 1e-6, errs
         tr = ctx.ll_trace(b)
         assert np.abs(tr - tro).max() < 1e-4
-        y = ctx.mwf(b).cpu().numpy()
-        yo = oracle.mwf(x, Po, lo, vo)
-        assert max(rel(y[n], yo[n]) for n in range(N)) < 1e-4
     ctx.close()
 
 

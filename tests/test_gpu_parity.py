@@ -1,11 +1,13 @@
 """GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
 
-Tolerances (from the target of the build): normwise relative error
-||gpu - oracle|| / ||oracle|| <= 1e-4 for v, lambda, P and every source image
-y_n after a fixed number of iterations from the same seeded init, and
-|LL_gpu - LL_oracle| <= 1e-6 nats per TF bin. The library computes the
-per-bin statistics in single precision and the IP update in double, so the
-trajectories differ only by single precision rounding.
+Tolerances: normwise relative error ||gpu - oracle|| / ||oracle|| <= 1e-4
+for v, lambda, P and every source image y_n after a fixed number of
+iterations from the same seeded init, over the whole array and for every
+frequency on its own, and |LL_gpu - LL_oracle| <= 1e-6 nats per TF bin. The
+per-bin error of v in the log domain (99.9th percentile) is gated at
+PER_BIN_TOL. The library computes the per-bin statistics in single precision
+and the IP update in double, so the trajectories differ only by single
+precision rounding.
 """
 import numpy as np
 import pytest
@@ -13,18 +15,14 @@ import torch
 
 import oracle
 from paper_2101_08563_amd import FastFCA, FastFCAError, synth
+from parity_metrics import rel, report
 
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
 REL_TOL = 1e-4
 LL_TOL = 1e-6
-
-
-def rel(a, b):
-    a = np.asarray(a)
-    b = np.asarray(b)
-    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+PER_BIN_TOL = 1e-3
 
 
 def to_dev(*arrs):
@@ -55,16 +53,22 @@ def run_gpu(x, P0, lam0, v0, iters, config=None, steps=None):
     return dict(P=P, lam=lam, v=v, ll=ll, trace=trace, y=y)
 
 
+def check_errors(errs):
+    for k in ("v", "lam", "P", "y", "v_f", "lam_f", "P_f", "y_f"):
+        if k in errs:
+            assert errs[k] <= REL_TOL, (k, errs)
+    assert errs["v_log999"] <= PER_BIN_TOL, errs
+    assert errs["ll"] <= LL_TOL, errs
+
+
 def check_against_oracle(x, P0, lam0, v0, iters, g, label):
     Po, lo, vo, tro = oracle.fit(x, P0, lam0, v0, iters, trace=True)
     llo, _ = oracle.loglik(x, Po, lo, vo)
-    errs = dict(v=rel(g["v"], vo), lam=rel(g["lam"], lo), P=rel(g["P"], Po), ll=abs(g["ll"] - llo))
     yo = oracle.mwf(x, Po, lo, vo)
-    errs["y"] = max(rel(g["y"][n], yo[n]) for n in range(yo.shape[0]))
-    print(label, errs, flush=True)
-    assert errs["v"] <= REL_TOL and errs["lam"] <= REL_TOL and errs["P"] <= REL_TOL, errs
-    assert errs["y"] <= REL_TOL, errs
-    assert errs["ll"] <= LL_TOL, errs
+    errs = report(g, Po, lo, vo, yo)
+    errs["ll"] = abs(g["ll"] - llo)
+    print(label, {k: "%.2e" % e for k, e in errs.items()}, flush=True)
+    check_errors(errs)
     # per-iteration trace (single precision per-bin terms, double accumulation)
     assert np.abs(g["trace"][: len(tro)] - tro).max() < 1e-4
     return errs
@@ -104,11 +108,15 @@ def general_start(F, M, seed):
 
 
 @pytest.mark.parametrize("M,N,rank,diffuse", [(3, 4, 3, 1e-2), (4, 6, 4, 1e-2), (4, 5, 2, 1e-1), (4, 6, 4, 1e-3),
-                                              (3, 4, 1, 1e-3)])
+                                              (3, 4, 1, 1e-3), (3, 2, 3, 1e-3), (2, 2, 2, 1e-3)])
 def test_ip_from_general_P_and_ill_conditioned_mixtures(M, N, rank, diffuse):
     """The M = 3, 4 sweep works through explicit inverses of P and of the Q_m:
     start from a general complex P (not the identity) and use mixtures whose
-    spatial covariances are close to low rank (small diffuse part)."""
+    spatial covariances are close to low rank (small diffuse part). The case
+    M = 3, N = 2, rank 3, diffuse 1e-3 fits poorly and its IP systems are
+    ill-conditioned: with the lane partials of Q_m added in single precision
+    it missed the likelihood bound (2.4e-6 nats per bin); tests/
+    test_fp32_statistics.py shows the cause on the CPU."""
     F, T, iters = 7, 300, 10
     x, _, lam0, v0 = make_case(F, T, M, N, rank=rank, diffuse=diffuse, config_id=30 + M, mixture_id=N)
     P0 = general_start(F, M, 1000 * M + N)
@@ -127,10 +135,10 @@ def test_launch_configurations_agree(threads, bpt):
 
 
 def test_minimum_T_equals_M():
+    """T = M frames, the fewest for which every Q_m can be nonsingular."""
     x, P0, lam0, v0 = make_case(5, 3, 3, 4, config_id=21)
     g = run_gpu(x, P0, lam0, v0, 3)
-    Po, lo, vo, _ = oracle.fit(x, P0, lam0, v0, 3)
-    assert rel(g["v"], vo) < 1e-3 and rel(g["P"], Po) < 1e-3
+    check_against_oracle(x, P0, lam0, v0, 3, g, "T = M = 3")
 
 
 def test_deterministic_and_resume_bitwise():
@@ -266,9 +274,10 @@ def test_ip_mm_algorithm2_parity(M, N, T, F):
     ctx.close()
     Po, lo, vo, tro = oracle.fit(x, P0, lam0, v0, 30, algo=1, trace=True)
     llo, _ = oracle.loglik(x, Po, lo, vo)
-    errs = dict(v=rel(v, vo), lam=rel(lam, lo), P=rel(P, Po), ll=abs(ll - llo))
-    print("mm", M, N, T, errs, flush=True)
-    assert errs["v"] < REL_TOL and errs["lam"] < REL_TOL and errs["P"] < REL_TOL and errs["ll"] < LL_TOL, errs
+    errs = report(dict(P=P, lam=lam, v=v), Po, lo, vo)
+    errs["ll"] = abs(ll - llo)
+    print("mm", M, N, T, {k: "%.2e" % e for k, e in errs.items()}, flush=True)
+    check_errors(errs)
     assert np.abs(trace - tro).max() < 1e-4
     assert np.diff(trace).min() > -1e-5
 
@@ -279,4 +288,25 @@ def test_ip_mm_rejected_for_wide_shapes():
     with pytest.raises(FastFCAError) as e:
         ctx.set_algorithm("mm")
     assert e.value.code == -7
+    ctx.close()
+
+
+def test_ll_alarm_reports_a_decrease():
+    """The likelihood alarm, forced from the host: a tolerance of -10 asks
+    for a gain of 10 nats per bin per iteration, so every frequency stops at
+    its second iteration with E_DECREASE; a restart at the default tolerance
+    runs clean (Algorithm 1 never lowers the likelihood)."""
+    x, P0, lam0, v0 = make_case(6, 200, 2, 3, config_id=29)
+    xd, Pd, ld, vd = to_dev(x, P0, lam0, v0)
+    ctx = FastFCA(xd, 3, Pd, ld, vd)
+    ctx.set_ll_alarm(-10.0)
+    ctx.em_step(5)
+    with pytest.raises(FastFCAError) as e:
+        ctx.sync()
+    assert e.value.code == -8 and "frequency 0" in str(e.value)
+    ctx.set_ll_alarm(1e-3)
+    ctx.set_params(Pd, ld, vd)
+    ctx.em_step(200)
+    ctx.sync()
+    assert np.diff(ctx.ll_trace()).min() > -1e-5
     ctx.close()
