@@ -9,10 +9,19 @@ Inputs are resident in HBM before timing starts.
 
 Metric: EM TF-bin*source updates per second = F*T*N*iterations / step time.
 
-Prints ONE JSON line (see the fields below). Options:
-  --gpus N (only 1 is supported), --steps K, --warmup W, --iters I,
-  --no-cpu (skip the oracle CPU baseline), --calib-copy MiB (also run a plain
-  device copy of that size, used to scale rocprofv3 byte counters).
+Prints ONE JSON line. Besides the contract fields it carries:
+  roofline         the EM kernel's ALU roofline: algorithmic flops per launch
+                   (flops_per_bin) over its event-timed duration against the
+                   published 157.3 TFLOP/s FP32 peak; beside it the kernel's
+                   own operation count against the one-FMA-per-lane rate and
+                   the HBM streaming-equivalent fractions
+  cpu_baseline     the FP64 oracle on all host cores and on one core
+  time_to_converge plain vs warm start, measured end to end (HIP events)
+  extra            the batch32, 256-mixture batch and large-array lines
+Options: --gpus N (only 1 is supported), --steps K, --warmup W, --iters I,
+  --no-cpu, --no-ttc, --no-extra, --ttc-mixtures K, --workload W (one line
+  for another workload), --calib-copy MiB (also run a plain device copy of
+  that size, used to scale rocprofv3 byte counters).
 """
 from __future__ import annotations
 
@@ -29,17 +38,28 @@ sys.path.insert(0, ROOT)
 
 # MI355X figures used for the roofline (per-unit derivations in the design doc).
 CU, SIMD_PER_CU, LANES, CLOCK_HZ = 256, 4, 16, 2.4e9
-FP32_FMA_PEAK = CU * SIMD_PER_CU * LANES * 2 * CLOCK_HZ      # 78.6 TFLOP/s, non-packed FP32 FMA
+FP32_PEAK = 157.3e12                                         # published FP32 vector peak (packed FMA)
+FP32_FMA_NONPACKED = CU * SIMD_PER_CU * LANES * 2 * CLOCK_HZ # 78.6 TFLOP/s, one FMA per lane per clock
 HBM_PEAK = 8.0e12                                            # bytes/s
 
 
-def em_flops_per_bin(M: int, N: int, algo: str = "em") -> int:
-    """Algorithmic flops per TF bin per iteration (FMA = 2 flops):
-    sigma^2 and its inverse (2MN + M), x x^H as M^2 real parameters (3M^2),
-    the M weighted covariances (2M^3), U = |P^H x|^2 (8M^2 + 3M), the
-    log-likelihood terms (4M), and the L/H update: for IP+EM the N sequential
-    source updates (N (2MN + 12M + 2)); for IP+MM the L-rule sums (2MN + 3M
-    + 4NM) and the H rule (2MN + 3M + 4NM + 3N)."""
+def flops_per_bin(M: int, N: int) -> int:
+    """Algorithmic flops per TF bin per IP+EM iteration, counted from the
+    method's definitions: the M weighted covariances of eq:wsampcov as
+    M(M+1)/2 Hermitian entries at (6 + 4M) flops each, U = |P^H x|^2 by
+    eq:Udef (8M^2), the N posterior updates of Algorithm 1 (15 MN) and the
+    log-likelihood terms of eq:negll (6M): 176 at (M, N) = (2, 3), 732 at
+    (4, 6), 3128 at (8, 10)."""
+    return M * (M + 1) // 2 * (6 + 4 * M) + 8 * M * M + 15 * M * N + 6 * M
+
+
+def kernel_ops_per_bin(M: int, N: int, algo: str = "em") -> int:
+    """Floating point operations per bin per iteration as the resident
+    kernel issues them (FMA = 2): sigma^2 and its inverse (2MN + M), x x^H as
+    M^2 real parameters (3M^2), the M weighted covariances (2M^3), U
+    (8M^2 + 3M), the log-likelihood terms (4M), and the L/H update: for
+    IP+EM the N sequential source updates (N (2MN + 12M + 2)); for IP+MM the
+    L-rule sums (2MN + 3M + 4NM) and the H rule (2MN + 3M + 4NM + 3N)."""
     common = (2 * M * N + M) + 3 * M * M + 2 * M ** 3 + (8 * M * M + 3 * M) + 4 * M
     if algo == "mm":
         return common + 2 * (2 * M * N + 3 * M + 4 * N * M) + 3 * N
@@ -47,8 +67,28 @@ def em_flops_per_bin(M: int, N: int, algo: str = "em") -> int:
 
 
 def em_bytes_per_bin(M: int, N: int) -> int:
-    """Algorithmic HBM bytes per TF bin per launch: read x (8M), read and write v (8N)."""
+    """HBM bytes per TF bin of one streaming pass (x read, v read and written): 8M + 8N."""
     return 8 * M + 8 * N
+
+
+def hbm_fracs(bins_by_shape, iters, seconds):
+    """Fractions of the HBM roofline: the updates/s achieved over the
+    updates/s of a design streaming 8M + 8N bytes per bin per iteration at
+    8 TB/s (x read once) and 16M + 8N (x read twice)."""
+    once = sum(b * (8 * M + 8 * N) for (M, N), b in bins_by_shape.items()) * iters
+    twice = sum(b * (16 * M + 8 * N) for (M, N), b in bins_by_shape.items()) * iters
+    return once / seconds / HBM_PEAK, twice / seconds / HBM_PEAK
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 KERNEL_FILES = ["em_item.hpp", "em_kernel.hip", "device.hpp", "internal.hpp", "ip_sm.hpp", "ip_wave.hpp"]
@@ -77,6 +117,22 @@ def measured_traffic():
     return d.get("traffic_bytes_per_launch")
 
 
+def roofline_alu(kernel, flops_8d, ops_kernel, seconds, bins_by_shape, iters, traffic=None):
+    """The ALU roofline object: achieved = algorithmic flops (flops_per_bin)
+    per launch over the measured time, against the published FP32 peak; the
+    kernel's own operation count against the one-FMA-per-lane rate and the
+    HBM streaming-equivalent fractions are reported beside it."""
+    ach = flops_8d / seconds
+    once, twice = hbm_fracs(bins_by_shape, iters, seconds)
+    return {"kernel": kernel, "bound": "alu", "achieved": ach / 1e12, "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": ach / FP32_PEAK, "traffic": traffic,
+            "flops_per_launch": flops_8d,
+            "kernel_ops_per_launch": ops_kernel,
+            "kernel_ops_frac_of_nonpacked_fp32": ops_kernel / seconds / FP32_FMA_NONPACKED,
+            "hbm_streaming_equivalent_frac_x_once": once,
+            "hbm_streaming_equivalent_frac_x_twice": twice}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +141,8 @@ def main():
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttc", action="store_true", help="skip the time-to-converge comparison")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batch and large-array workloads")
+    ap.add_argument("--ttc-mixtures", type=int, default=64)
     ap.add_argument("--algo", choices=["em", "mm"], default="em",
                     help="headline update: Algorithm 1 (IP+EM, the contract line) or Algorithm 2 (IP+MM)")
     ap.add_argument("--calib-copy", type=int, default=0)
@@ -92,11 +150,11 @@ def main():
     ap.add_argument("--bpt", type=int, default=0)
     ap.add_argument("--workload", choices=["headline", "batch", "batch32", "large", "blocks", "mnmf"],
                     default="headline",
-                    help="headline: the contract line (M=2 N=3 F=513 T=1000); batch: 256 mixed "
-                         "mixtures in one persistent launch vs sequential runs; large: M=8 N=10 "
-                         "F=1025 T=4000; batch32: 32 headline-shaped mixtures in one context; "
-                         "blocks: the piecewise stationary model on the headline "
-                         "mixture (B=4); mnmf: FastMNMF on the headline mixture (K=8)")
+                    help="headline: the contract line (M=2 N=3 F=513 T=1000), with the batch32, batch "
+                         "and large lines under 'extra'; batch: 256 mixed mixtures against sequential runs; "
+                         "large: M=8 N=10 F=1025 T=4000; batch32: 32 headline-shaped mixtures in one context; "
+                         "blocks: the piecewise stationary model on the headline mixture (B=4); mnmf: "
+                         "FastMNMF on the headline mixture (K=8)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build measures the single-GPU kernel "
@@ -104,16 +162,11 @@ def main():
               "--gpus %d is not supported." % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    if args.workload == "batch":
-        return bench_batch(args)
-    if args.workload == "large":
-        return bench_large(args)
-    if args.workload == "batch32":
-        return bench_batch32(args)
-    if args.workload == "blocks":
-        return bench_blocks(args)
-    if args.workload == "mnmf":
-        return bench_mnmf(args)
+    single = {"batch": bench_batch, "large": bench_large, "batch32": bench_batch32, "blocks": bench_blocks,
+              "mnmf": bench_mnmf}
+    if args.workload in single:
+        print(json.dumps(single[args.workload](args)))
+        return
 
     import torch
 
@@ -171,9 +224,6 @@ def main():
 
     updates = F * T * N * iters
     value = updates / (ms_per_step * 1e-3)
-    flops = em_flops_per_bin(M, N, args.algo) * F * T * iters
-    achieved = flops / (em_ms * 1e-3)
-    hbm_bytes = em_bytes_per_bin(M, N) * F * T
     out = {
         "metric": "EM TF-bin*source updates/s",
         "value": value,
@@ -190,20 +240,13 @@ def main():
         "config": {"workload": "FastFCA IP+%s x%d + MWF, M=%d N=%d F=%d T=%d" % (args.algo.upper(), iters, M, N, F, T),
                    "M": M, "N": N, "F": F, "T": T, "iters": iters, "threads": threads,
                    "bins_per_thread": bpt, "ll_per_bin": ll},
-        "roofline": {
-            "kernel": "em_kernel<%d,%d,%d> (IP+%s, state resident on chip)" % (M, N, bpt, args.algo.upper()),
-            "bound": "alu",
-            "achieved": achieved / 1e12,
-            "peak": FP32_FMA_PEAK / 1e12,
-            "unit": "TFLOP/s",
-            "frac": achieved / FP32_FMA_PEAK,
-            "traffic": measured_traffic() if (iters == 100 and args.algo == "em") else None,
-            "em_ms_per_launch": em_ms,
-            "flops_per_launch": flops,
-            "hbm_algorithmic_bytes_per_launch": hbm_bytes,
-            "hbm_GBps_algorithmic": hbm_bytes / (em_ms * 1e-3) / 1e9,
-        },
+        "roofline": roofline_alu("em_kernel<%d,%d,%d> (IP+%s, state resident on chip)" % (M, N, bpt, args.algo.upper()),
+                                 flops_per_bin(M, N) * F * T * iters, kernel_ops_per_bin(M, N, args.algo) * F * T * iters,
+                                 em_ms * 1e-3, {(M, N): F * T}, iters,
+                                 traffic=measured_traffic() if (iters == 100 and args.algo == "em") else None),
     }
+    out["roofline"]["em_ms_per_launch"] = em_ms
+    out["roofline"]["hbm_algorithmic_bytes_per_launch"] = em_bytes_per_bin(M, N) * F * T
     if args.calib_copy:
         n = args.calib_copy * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device=dev)
@@ -215,44 +258,63 @@ def main():
 
     if not args.no_cpu:
         import oracle
+        cores = oracle.num_threads()
         t2 = time.perf_counter()
-        Po, lo, vo, _ = oracle.fit(x, P0, lam0, v0, iters)
+        Po, lo, vo, _ = oracle.fit(x, P0, lam0, v0, iters, nthreads=cores)
         oracle.mwf(x, Po, lo, vo)
         t3 = time.perf_counter()
+        # one core: the first 32 frequencies of the same workload
+        F1 = 32
+        t4 = time.perf_counter()
+        oracle.fit(x[:F1], P0[:F1], lam0[:F1], v0[:F1], iters, nthreads=1)
+        t5 = time.perf_counter()
+        oracle.fit(x[:1], P0[:1], lam0[:1], v0[:1], 1, nthreads=cores)  # back to every core
         out["cpu_baseline"] = {
             "value": updates / (t3 - t2),
             "unit": "updates/s",
-            "cores": oracle.num_threads(),
+            "cores": cores,
             "kind": "oracle",
             "sample": "full workload: F=%d T=%d M=%d N=%d, %d IP+EM iterations + MWF, FP64 C, OpenMP over "
                       "frequencies, %.2f s" % (F, T, M, N, iters, t3 - t2),
+            "cpu_model": cpu_model(),
+            "one_core": {"value": F1 * T * N * iters / (t5 - t4), "unit": "updates/s", "cores": 1,
+                         "sample": "F=%d of %d frequencies, %d IP+EM iterations, %.2f s" % (F1, F, iters, t5 - t4)},
         }
     ctx.close()
     if not args.no_ttc:
-        out["time_to_converge"] = time_to_converge()
+        out["time_to_converge"] = time_to_converge(args.ttc_mixtures)
+    if not args.no_extra:
+        sub = argparse.Namespace(**vars(args))
+        sub.iters = 100
+        sub.no_cpu = True
+        out["extra"] = {}
+        for name, fn in (("batch32", bench_batch32), ("batch256", bench_batch), ("large", bench_large)):
+            try:
+                r = fn(sub)
+                out["extra"][name] = {k: r[k] for k in ("value", "unit", "ms_per_step")}
+                out["extra"][name]["workload"] = r["config"]["workload"]
+                out["extra"][name]["roofline"] = r["roofline"]
+            except Exception as e:  # reported, not hidden
+                out["extra"][name] = {"error": "%s: %s" % (type(e).__name__, e)}
     print(json.dumps(out))
 
 
-def time_to_converge(n_eval=4, conv_iters=1500):
-    """Second half of the metric: wall time for plain IP+EM and for the learned
-    warm start (features + network + IP+EM) to reach the plain fit's
-    log-likelihood after conv_iters iterations minus 1e-2 nats/bin, medians over
-    n_eval held-out headline-shaped mixtures (paper_2101_08563_amd.train_warmstart)."""
+def time_to_converge(n_eval=64, conv_iters=1500):
+    """Second half of the metric, measured end to end: wall time for plain
+    IP+EM and for the warm start (fastfca_warmstart: features, network,
+    judge; then IP+EM) to reach the plain fit's log-likelihood after
+    conv_iters iterations minus 1e-2 nats/bin, medians over n_eval held-out
+    headline-shaped mixtures (paper_2101_08563_amd.train_warmstart.measure)."""
     import contextlib
 
     weights = os.path.join(ROOT, "paper_2101_08563_amd", "data", "warmstart_c64l6.npz")
     try:
         from paper_2101_08563_amd import train_warmstart
         with contextlib.redirect_stdout(sys.stderr):
-            s = train_warmstart.evaluate(weights, n_eval=n_eval, conv_iters=conv_iters, batch=n_eval)
+            s, _ = train_warmstart.measure(weights, n_eval=n_eval, conv_iters=conv_iters)
     except Exception as e:  # reported, not hidden: the line still carries the throughput
         return {"error": "%s: %s" % (type(e).__name__, e)}
-    keys = ("plain_ms_median", "warm_ms_median", "plain_iters_median", "warm_iters_median",
-            "perfect_net_iters_median", "warmstart_ms", "em_ms_per_iter", "warm_faster_frac")
-    r = {k: s.get(k) for k in keys}
-    r.update({"tol_nats_per_bin": s.get("tol_nats_per_bin"), "mixtures": s.get("n_eval"),
-              "reference_iters": conv_iters})
-    return r
+    return s
 
 
 def _time(fn, stream, reps):
@@ -268,10 +330,18 @@ def _time(fn, stream, reps):
     return float(np.median(ts))
 
 
+def _line(value, ms, reps, workload, roofline, **config):
+    return {"metric": "EM TF-bin*source updates/s", "value": value, "unit": "updates/s", "n_gpus": 1,
+            "steps": reps, "warmup": 1, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": dict(workload=workload, **config),
+            "roofline": roofline}
+
+
 def bench_batch(args):
     """256 mixtures with T ~ U{200..2000}, M in {2,3,4}, N in {M+1, M+2}, F=513,
-    drawn on the GPU; one persistent launch per em_step call, against the same
-    mixtures run one context at a time."""
+    drawn on the GPU; the autotuned schedule (class launches or one
+    persistent launch) per em_step call, against the same mixtures run one
+    context at a time."""
     import torch
 
     from paper_2101_08563_amd import FastFCA, synth
@@ -295,7 +365,8 @@ def bench_batch(args):
             tune = json.loads(fh.read().splitlines()[-1])
     batch.em_step(2)
     batch.sync()
-    t_batch = _time(lambda: batch.em_step(iters), stream, max(2, args.steps // 5))
+    reps = max(2, args.steps // 5)
+    t_batch = _time(lambda: batch.em_step(iters), stream, reps)
     batch.sync()
     batch.close()
     singles = [FastFCA(x, s["N"], seed=1 + i, stream=stream) for i, (x, s) in enumerate(zip(xs, specs))]
@@ -312,8 +383,18 @@ def bench_batch(args):
         c.close()
     updates = sum(s["F"] * s["T"] * s["N"] for s in specs) * iters
     bins = sum(s["F"] * s["T"] for s in specs)
-    flops = sum(s["F"] * s["T"] * em_flops_per_bin(s["M"], s["N"]) for s in specs) * iters
-    oracle_sample = None
+    shapes = {}
+    for s in specs:
+        shapes[(s["M"], s["N"])] = shapes.get((s["M"], s["N"]), 0) + s["F"] * s["T"]
+    fl = sum(b * flops_per_bin(M, N) for (M, N), b in shapes.items()) * iters
+    ops = sum(b * kernel_ops_per_bin(M, N) for (M, N), b in shapes.items()) * iters
+    out = _line(updates / (t_batch * 1e-3), t_batch, reps,
+                "batch: 256 mixtures, T~U{200..2000}, M in {2,3,4}, N in {M+1,M+2}, F=513, %d IP+EM iterations, %s"
+                % (iters, "one persistent launch" if tune["persistent"] else "one launch per (M, N, T-bucket) class"),
+                roofline_alu("em_persistent_kernel" if tune["persistent"] else "em_kernel class launches", fl, ops,
+                             t_batch * 1e-3, shapes, iters),
+                iters=iters, tf_bins=bins, autotune=tune, sequential_ms=t_seq, speedup_vs_sequential=t_seq / t_batch,
+                sequential_updates_per_s=updates / (t_seq * 1e-3))
     if not args.no_cpu:
         # the oracle on a bounded sample: the first 16 mixtures, 128 frequencies each, 10 iterations
         import oracle
@@ -326,31 +407,17 @@ def bench_batch(args):
             oracle.fit(xh, P0, l0, v0, 10)
             t_cpu += time.perf_counter() - t2
             upd_cpu += xh.shape[0] * xh.shape[1] * s["N"] * 10
-        oracle_sample = {"value": upd_cpu / t_cpu, "unit": "updates/s", "cores": oracle.num_threads(), "kind": "oracle",
-                         "sample": "16 of 256 mixtures, 128 of 513 frequencies each, 10 iterations, %.2f s" % t_cpu}
-    out = {"metric": "EM TF-bin*source updates/s", "value": updates / (t_batch * 1e-3), "unit": "updates/s",
-           "n_gpus": 1, "steps": max(2, args.steps // 5), "warmup": 1, "ms_per_step": t_batch,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-           "data": "synthetic",
-           "config": {"workload": "batch: 256 mixtures, T~U{200..2000}, M in {2,3,4}, N in {M+1,M+2}, F=513, "
-                                  "%d IP+EM iterations, %s" % (iters, "one persistent launch" if tune["persistent"]
-                                                               else "one launch per (M, N, T-bucket) class"),
-                      "iters": iters, "tf_bins": bins, "autotune": tune,
-                      "sequential_ms": t_seq, "speedup_vs_sequential": t_seq / t_batch,
-                      "sequential_updates_per_s": updates / (t_seq * 1e-3)},
-           "roofline": {"kernel": "em_persistent_kernel" if tune["persistent"] else "em_kernel class launches",
-                        "bound": "alu",
-                        "achieved": flops / (t_batch * 1e-3) / 1e12, "peak": FP32_FMA_PEAK / 1e12,
-                        "unit": "TFLOP/s", "frac": flops / (t_batch * 1e-3) / FP32_FMA_PEAK, "traffic": None}}
-    if oracle_sample:
-        out["cpu_baseline"] = oracle_sample
-    print(json.dumps(out))
+        out["cpu_baseline"] = {"value": upd_cpu / t_cpu, "unit": "updates/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "cpu_model": cpu_model(),
+                               "sample": "16 of 256 mixtures, 128 of 513 frequencies each, 10 iterations, %.2f s"
+                                         % t_cpu}
+    return out
 
 
 def bench_batch32(args, B=32):
     """B mixtures of the headline shape (M=2 N=3 F=513 T=1000, different seeds)
     in one context: the same kernel as the headline line, with enough
-    workgroups (B x 513) that no CU runs a third frequency alone at the end."""
+    workgroups (B x 513) to fill the chip."""
     import torch
 
     from paper_2101_08563_amd import FastFCA
@@ -369,19 +436,12 @@ def bench_batch32(args, B=32):
     ctx.sync()
     threads, bpt = ctx.get_config()
     ctx.close()
-    updates = B * F * T * N * iters
-    flops = em_flops_per_bin(M, N) * B * F * T * iters
-    single_pass = (8 * M + 8 * N) * B * F * T * iters  # one HBM pass per iteration (x read, v read and written)
-    print(json.dumps({"metric": "EM TF-bin*source updates/s", "value": updates / (t * 1e-3), "unit": "updates/s",
-                      "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": t, "higher_is_better": True,
-                      "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-                      "config": {"workload": "%d headline-shaped mixtures (M=2 N=3 F=513 T=1000), %d IP+EM "
-                                             "iterations, one context" % (B, iters),
-                                 "threads": threads, "bins_per_thread": bpt,
-                                 "single_pass_hbm_equivalent_GBps": single_pass / (t * 1e-3) / 1e9},
-                      "roofline": {"kernel": "em_kernel<2,3,%d>" % bpt, "bound": "alu",
-                                   "achieved": flops / (t * 1e-3) / 1e12, "peak": FP32_FMA_PEAK / 1e12,
-                                   "unit": "TFLOP/s", "frac": flops / (t * 1e-3) / FP32_FMA_PEAK, "traffic": None}}))
+    bins = B * F * T
+    return _line(bins * N * iters / (t * 1e-3), t, reps,
+                 "%d headline-shaped mixtures (M=2 N=3 F=513 T=1000), %d IP+EM iterations, one context" % (B, iters),
+                 roofline_alu("em_kernel<2,3,%d>" % bpt, flops_per_bin(M, N) * bins * iters,
+                              kernel_ops_per_bin(M, N) * bins * iters, t * 1e-3, {(M, N): bins}, iters),
+                 threads=threads, bins_per_thread=bpt)
 
 
 def bench_large(args):
@@ -399,7 +459,8 @@ def bench_large(args):
     ctx = FastFCA(x, N, seed=3, stream=stream)
     ctx.em_step(1)
     ctx.sync()
-    t = _time(lambda: ctx.em_step(iters), stream, 3)
+    reps = 3
+    t = _time(lambda: ctx.em_step(iters), stream, reps)
     threads, bpt = ctx.get_config()
     ll = ctx.loglik()
     cpu = None
@@ -415,22 +476,18 @@ def bench_large(args):
         oracle.fit(xs, P0, l0, v0, its)
         t3 = time.perf_counter()
         cpu = {"value": Fs * T * N * its / (t3 - t2), "unit": "updates/s", "cores": oracle.num_threads(),
-               "kind": "oracle", "sample": "F=%d of %d frequencies, %d iterations, %.2f s" % (Fs, F, its, t3 - t2)}
+               "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": "F=%d of %d frequencies, %d iterations, %.2f s" % (Fs, F, its, t3 - t2)}
     ctx.close()
-    updates = F * T * N * iters
-    flops = em_flops_per_bin(M, N) * F * T * iters
-    out = {"metric": "EM TF-bin*source updates/s", "value": updates / (t * 1e-3), "unit": "updates/s", "n_gpus": 1,
-           "steps": 3, "warmup": 1, "ms_per_step": t, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "large array: M=8 N=10 F=1025 T=4000, %d IP+EM iterations" % iters,
-                      "threads": threads, "bins_per_thread": bpt, "ll_per_bin": ll},
-           "roofline": {"kernel": "em_wide_kernel<8,10,%d>" % bpt, "bound": "alu",
-                        "achieved": flops / (t * 1e-3) / 1e12, "peak": FP32_FMA_PEAK / 1e12, "unit": "TFLOP/s",
-                        "frac": flops / (t * 1e-3) / FP32_FMA_PEAK, "traffic": None,
-                        "hbm_GBps_algorithmic": (16 * M * iters + 8 * N) * F * T / (t * 1e-3) / 1e9}}
+    bins = F * T
+    out = _line(bins * N * iters / (t * 1e-3), t, reps,
+                "large array: M=8 N=10 F=1025 T=4000, %d IP+EM iterations" % iters,
+                roofline_alu("em_wide_kernel<8,10,%d>" % bpt, flops_per_bin(M, N) * bins * iters,
+                             kernel_ops_per_bin(M, N) * bins * iters, t * 1e-3, {(M, N): bins}, iters),
+                threads=threads, bins_per_thread=bpt, ll_per_bin=ll)
     if cpu:
         out["cpu_baseline"] = cpu
-    print(json.dumps(out))
+    return out
 
 
 def _headline_mixture():
@@ -468,19 +525,16 @@ def bench_blocks(args, B=4):
     ctx.close()
     J = T // B
     updates = F * J * N * iters
-    # flops per block and iteration: as em_flops_per_bin, with Q_m taking the
-    # block covariance directly (2M^3) and U a dot product of its M^2 parameters (2M^3)
-    fl = (2 * M * N + M) + 2 * M ** 3 + 2 * M ** 3 + N * (2 * M * N + 12 * M + 2) + 4 * M
-    out = {"metric": "EM TF-bin*source updates/s", "value": updates / (t * 1e-3), "unit": "updates/s",
-           "n_gpus": 1, "steps": max(3, args.steps // 4), "warmup": 1, "ms_per_step": t,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-           "data": "synthetic",
-           "config": {"workload": "piecewise stationary model, blocks of %d frames: M=%d N=%d F=%d "
-                                  "T=%d (J=%d blocks), %d IP+EM iterations" % (B, M, N, F, T, J, iters),
-                      "frames_per_s": F * T * iters / (t * 1e-3)},
-           "roofline": {"bound": "alu", "achieved": fl * F * J * iters / (t * 1e-3) / 1e12,
-                        "peak": FP32_FMA_PEAK / 1e12, "unit": "TFLOP/s",
-                        "frac": fl * F * J * iters / (t * 1e-3) / FP32_FMA_PEAK, "traffic": None}}
+    # flops per block and iteration: as flops_per_bin, with Q_m taking the
+    # given block covariance (M(M+1)/2 entries at 4M flops) and U a dot
+    # product of its M^2 parameters (2M^3)
+    fl = M * (M + 1) // 2 * 4 * M + 2 * M ** 3 + 15 * M * N + 6 * M
+    out = _line(updates / (t * 1e-3), t, max(3, args.steps // 4),
+                "piecewise stationary model, blocks of %d frames: M=%d N=%d F=%d T=%d (J=%d blocks), "
+                "%d IP+EM iterations" % (B, M, N, F, T, J, iters),
+                {"bound": "alu", "achieved": fl * F * J * iters / (t * 1e-3) / 1e12, "peak": FP32_PEAK / 1e12,
+                 "unit": "TFLOP/s", "frac": fl * F * J * iters / (t * 1e-3) / FP32_PEAK, "traffic": None},
+                frames_per_s=F * T * iters / (t * 1e-3))
     if not args.no_cpu:
         import oracle
         t2 = time.perf_counter()
@@ -488,7 +542,7 @@ def bench_blocks(args, B=4):
         t3 = time.perf_counter()
         out["cpu_baseline"] = {"value": updates / (t3 - t2), "unit": "updates/s", "cores": oracle.num_threads(),
                                "kind": "oracle", "sample": "full workload, %d iterations, %.2f s" % (iters, t3 - t2)}
-    print(json.dumps(out))
+    return out
 
 
 def bench_mnmf(args, K=8):
@@ -520,14 +574,11 @@ def bench_mnmf(args, K=8):
     ctx.close()
     updates = F * T * N * iters
     hbm = (8 * M + 16 * N) * F * T * iters   # x read; G, E written and read back, per iteration
-    out = {"metric": "EM TF-bin*source updates/s", "value": updates / (t * 1e-3), "unit": "updates/s",
-           "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": t, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "FastMNMF: M=%d N=%d K=%d F=%d T=%d, %d IP+MM iterations"
-                                  % (M, N, K, F, T, iters), "ll_per_bin": ll,
-                      "us_per_iteration": t * 1e3 / iters},
-           "roofline": {"bound": "hbm", "achieved": hbm / (t * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
-                        "unit": "GB/s", "frac": hbm / (t * 1e-3) / HBM_PEAK, "traffic": None}}
+    out = _line(updates / (t * 1e-3), t, reps,
+                "FastMNMF: M=%d N=%d K=%d F=%d T=%d, %d IP+MM iterations" % (M, N, K, F, T, iters),
+                {"bound": "hbm", "achieved": hbm / (t * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
+                 "unit": "GB/s", "frac": hbm / (t * 1e-3) / HBM_PEAK, "traffic": None},
+                ll_per_bin=ll, us_per_iteration=t * 1e3 / iters)
     if not args.no_cpu:
         # the oracle (single thread: the frequencies are coupled through V) on
         # the full mixture for 5 iterations
@@ -539,7 +590,7 @@ def bench_mnmf(args, K=8):
         out["cpu_baseline"] = {"value": Fs * T * N * its / (t3 - t2), "unit": "updates/s", "cores": 1,
                                "kind": "oracle", "sample": "F=%d of %d frequencies, %d iterations, %.2f s"
                                                            % (Fs, F, its, t3 - t2)}
-    print(json.dumps(out))
+    return out
 
 
 if __name__ == "__main__":

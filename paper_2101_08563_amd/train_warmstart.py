@@ -12,16 +12,15 @@ Targets: the IP+EM fit of each training mixture after --fit-iters iterations
 from the library's seeded initialization, trace-normalized and expressed in
 the whitened basis P0 = C_f^{-1/2} (fastfca_ws_targets).
 
-Evaluation (per held-out mixture): LL* = the plain fit's log-likelihood per
-bin after --conv-iters iterations; iterations (and wall time) to reach
-LL* - 1e-2 from (a) the seeded initialization, (b) the network's warm start
-(P0, exp(lambda_hat), exp(v_hat)) and (c) a whitening-only start (P0,
-lambda = 1, v = whitened power / N); for diagnosis also (d) the plain fit's
-own targets fed back through the warm-start path (a perfect network), (e)
-its lambda with the power-based v and (f) the network's lambda with the
-power-based v. The warm start is judged by its initial
-log-likelihood: if it is not finite or below that of the seeded start, the
-seeded start is used (fallback).
+Evaluation (per held-out mixture, measure()): LL* = the plain fit's
+log-likelihood per bin after --conv-iters iterations from the library's
+seeded start; iterations to LL* - 1e-2 from (a) the seeded start, (b)
+fastfca_warmstart with the network, (c) fastfca_warmstart without it (the
+whitening-only start), and, as a bound, (d) the plain fit's own targets fed
+back through the warm-start path (a perfect network). The library's
+fastfca_warmstart judges every start per frequency by its log-likelihood and
+keeps the seeded start where the new one is worse. Wall times of (a) and
+(b) are measured end to end with HIP events.
 """
 from __future__ import annotations
 
@@ -73,150 +72,115 @@ def _iters_to(trace, target):
     return int(idx[0]) + 1 if len(idx) else None
 
 
-def _time_em(ctx, k, reps=3):
-    s = torch.cuda.current_stream()
-    best = 1e30
-    for _ in range(reps):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(s)
-        ctx.em_step(k)
-        b.record(s)
-        b.synchronize()
-        best = min(best, a.elapsed_time(b))
-    return best
-
-
-def _med(res, key):
-    a = np.array([r[key] if r[key] is not None else np.nan for r in res], float)
-    return float(np.nanmedian(a)) if np.isfinite(a).any() else None
-
-
 def cmd_eval(args):
-    summary = evaluate(args.weights, args.n_eval, args.conv_iters, args.batch, args.out)
-    return summary
-
-
-def evaluate(weights, n_eval, conv_iters, batch, out=""):
-    """Run the evaluation arms on n_eval held-out mixtures; returns the summary dict."""
-    args = argparse.Namespace(weights=weights, n_eval=n_eval, conv_iters=conv_iters, batch=batch, out=out)
-    net = ConvNet.load(args.weights)
-    res = []
-    t0 = time.time()
-    # per-iteration cost and warm-start overhead, measured on one mixture
-    x = synth_mixture(F, T, M, N, seed=10**6)
-    ctx = FastFCA(x, N, seed=1)
-    ctx.em_step(10)
-    t10 = _time_em(ctx, 10)
-    t110 = _time_em(ctx, 110)
-    t_iter = (t110 - t10) / 100.0
-    t_fixed = t10 - 10 * t_iter
-    ctx.close()
-    s = torch.cuda.current_stream()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for _ in range(2):
-        a.record(s)
-        warmstart.warm_init(net, x)
-        b.record(s)
-        b.synchronize()
-    t_ws = a.elapsed_time(b)
-    log("EM %.4f ms/iteration + %.4f ms per call; warm start (features + network) %.3f ms" % (t_iter, t_fixed, t_ws))
-    B = args.batch
-    for a0 in range(0, args.n_eval, B):
-        ids = list(range(a0, min(args.n_eval, a0 + B)))
-        xs = [synth_mixture(F, T, M, N, seed=10**6 + i) for i in ids]
-        # (a) plain: seeded init
-        plain = FastFCA.from_batch([dict(x=x, N=N) for x in xs], seed=10**6 + a0)
-        ll_plain0 = [plain.loglik(b) for b in range(len(xs))]
-        p_init = [plain.get_params(b) for b in range(len(xs))]
-        plain.em_step(args.conv_iters)
-        tr_plain = [plain.ll_trace(b) for b in range(len(xs))]
-        # (d) a perfect network: the plain fit's own targets fed back through
-        # the warm-start path (an upper bound on what the network can gain)
-        probs_p, lam_perfect = [], []
-        for b, x in enumerate(xs):
-            P, lam, v = plain.get_params(b)
-            P0, _ = warmstart.features(x)
-            tv, tl = warmstart.targets(P, lam, v, P0)
-            lam_p, v_p = warmstart.apply_outputs(tv, tl.view(F, N, M), M)
-            probs_p.append(dict(x=x, N=N, P0=P0, lam0=lam_p, v0=v_p))
-            lam_perfect.append(lam_p)
-        plain.close()
-        perfect = FastFCA.from_batch(probs_p)
-        perfect.em_step(args.conv_iters)
-        tr_perf = [perfect.ll_trace(b) for b in range(len(xs))]
-        perfect.close()
-        # (b) warm start, (c) whitening only
-        probs_w, probs_h, judged = [], [], []
-        for b, x in enumerate(xs):
-            P0, lam, v = warmstart.warm_init(net, x)
-            probs_w.append(dict(x=x, N=N, P0=P0, lam0=lam, v0=v))
-            _, feat = None, None
-            pw = (torch.abs(torch.einsum("frm,ftr->ftm", P0.conj().to(torch.complex64), x)) ** 2)
-            vh = (pw.mean(dim=2, keepdim=True) / N).repeat(1, 1, N).contiguous().float()
-            probs_h.append(dict(x=x, N=N, P0=P0, lam0=torch.ones((F, N, M), device=x.device), v0=vh))
-        warm = FastFCA.from_batch(probs_w)
-        ll_warm0 = [warm.loglik(b) for b in range(len(xs))]
-        for b in range(len(xs)):
-            ok = np.isfinite(ll_warm0[b]) and ll_warm0[b] >= ll_plain0[b]
-            judged.append(ok)
-            if not ok:  # fallback: the seeded start
-                warm.set_params(*p_init[b], b=b)
-        warm.em_step(args.conv_iters)
-        tr_warm = [warm.ll_trace(b) for b in range(len(xs))]
-        warm.close()
-        heur = FastFCA.from_batch(probs_h)
-        heur.em_step(args.conv_iters)
-        tr_heur = [heur.ll_trace(b) for b in range(len(xs))]
-        heur.close()
-        # (e) perfect lambda with the power-based v, (f) network lambda with the power-based v
-        pl = FastFCA.from_batch([dict(ph, lam0=lp) for ph, lp in zip(probs_h, lam_perfect)])
-        pl.em_step(args.conv_iters)
-        tr_pl = [pl.ll_trace(b) for b in range(len(xs))]
-        pl.close()
-        nl = FastFCA.from_batch([dict(ph, lam0=pw["lam0"]) for ph, pw in zip(probs_h, probs_w)])
-        nl.em_step(args.conv_iters)
-        tr_nl = [nl.ll_trace(b) for b in range(len(xs))]
-        nl.close()
-        for b, i in enumerate(ids):
-            llstar = float(tr_plain[b][-1])
-            kp = _iters_to(tr_plain[b], llstar - TOL)
-            kw = _iters_to(tr_warm[b], llstar - TOL)
-            kh = _iters_to(tr_heur[b], llstar - TOL)
-            kpf = _iters_to(tr_perf[b], llstar - TOL)
-            res.append(dict(id=i, ll_star=llstar, ll_warm_final=float(tr_warm[b][-1]), k_plain=kp, k_warm=kw,
-                            k_heur=kh, k_perfect=kpf, k_perfect_lam=_iters_to(tr_pl[b], llstar - TOL),
-                            k_net_lam=_iters_to(tr_nl[b], llstar - TOL), warm_used=bool(judged[b]),
-                            ll0_plain=ll_plain0[b], ll0_warm=ll_warm0[b]))
-        log("eval %d/%d mixtures (%.1f s)" % (len(res), args.n_eval, time.time() - t0))
-
-    def wall(k, extra=0.0):
-        return None if k is None else t_fixed + k * t_iter + extra
-
-    kp = np.array([r["k_plain"] for r in res], float)
-    kw = np.array([r["k_warm"] if r["k_warm"] is not None else np.nan for r in res], float)
-    kh = np.array([r["k_heur"] if r["k_heur"] is not None else np.nan for r in res], float)
-    kpf = np.array([r["k_perfect"] if r["k_perfect"] is not None else np.nan for r in res], float)
-    wp = np.array([wall(r["k_plain"]) for r in res], float)
-    ww = np.array([wall(r["k_warm"], t_ws) if r["k_warm"] is not None else np.nan for r in res], float)
-    summary = {
-        "n_eval": len(res), "tol_nats_per_bin": TOL, "conv_iters": args.conv_iters,
-        "em_ms_per_iter": t_iter, "em_ms_per_call": t_fixed, "warmstart_ms": t_ws,
-        "plain_iters_median": float(np.nanmedian(kp)), "warm_iters_median": float(np.nanmedian(kw)),
-        "heur_iters_median": float(np.nanmedian(kh)) if np.isfinite(kh).any() else None,
-        "perfect_net_iters_median": float(np.nanmedian(kpf)) if np.isfinite(kpf).any() else None,
-        "perfect_lambda_power_v_iters_median": _med(res, "k_perfect_lam"),
-        "net_lambda_power_v_iters_median": _med(res, "k_net_lam"),
-        "plain_ms_median": float(np.nanmedian(wp)), "warm_ms_median": float(np.nanmedian(ww)),
-        "warm_reached_frac": float(np.isfinite(kw).mean()), "heur_reached_frac": float(np.isfinite(kh).mean()),
-        "warm_faster_frac": float(np.nanmean(np.where(np.isfinite(ww), ww < wp, False))),
-        "warm_used_frac": float(np.mean([r["warm_used"] for r in res])),
-        "ll_warm_minus_star_median": float(np.median([r["ll_warm_final"] - r["ll_star"] for r in res])),
-    }
+    summary, rows = measure(args.weights, args.n_eval, args.conv_iters, log=log)
     log(json.dumps(summary))
     if args.out:
         with open(args.out, "w") as fh:
-            json.dump({"summary": summary, "per_mixture": res}, fh)
+            json.dump({"summary": summary, "per_mixture": rows}, fh)
     return summary
+
+
+def _timed(stream, fn, reps=3):
+    """Median over reps of the event time (ms) of fn() on stream."""
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def measure(weights, n_eval=64, conv_iters=1500, seed0=10**6, log=None):
+    """Measured time to converge on n_eval held-out mixtures (seeds seed0 + i,
+    disjoint from the training seeds), one single-mixture context each.
+
+    LL* is the plain fit's log-likelihood per bin after conv_iters iterations
+    from the library's seeded start; k_plain, k_warm, k_heur are the
+    iterations to LL* - TOL from the seeded start, from fastfca_warmstart with
+    the network, and from fastfca_warmstart without it (whitening only). The
+    wall times are measured end to end with HIP events on the context's
+    stream, each the median of three repetitions from the same start:
+      plain  em_step(k_plain)
+      warm   fastfca_warmstart(net) (features, network, judge) + em_step(k_warm)
+    (the graph of each em_step length is captured before its timed runs)."""
+    net = ConvNet.load(weights)
+    stream = torch.cuda.current_stream()
+    rows = []
+    t0 = time.time()
+    for i in range(n_eval):
+        x = synth_mixture(F, T, M, N, seed=seed0 + i)
+        ctx = FastFCA(x, N, seed=seed0 + i)
+        P0, l0, v0 = (a.clone() for a in ctx.get_params())
+
+        def restart():
+            ctx.set_params(P0, l0, v0)
+
+        ctx.em_step(conv_iters)
+        tr_p = ctx.ll_trace()
+        llstar = float(tr_p[-1])
+        target = llstar - TOL
+        kp = _iters_to(tr_p, target)
+        restart()
+        taken = ctx.warmstart(net, count=True)
+        ctx.em_step(conv_iters)
+        kw = _iters_to(ctx.ll_trace(), target)
+        restart()
+        ctx.warmstart(None)
+        ctx.em_step(conv_iters)
+        kh = _iters_to(ctx.ll_trace(), target)
+        # a perfect network: the plain fit's own targets through the same path
+        restart()
+        ctx.em_step(conv_iters)
+        Pf, lf, vf = ctx.get_params()
+        Pw, _ = warmstart.features(x)
+        tv, tl = warmstart.targets(Pf, lf, vf, Pw)
+        lam_p, v_p = warmstart.apply_outputs(tv, tl.view(F, N, M), M)
+        ctx.set_params(Pw, lam_p, v_p)
+        ctx.em_step(conv_iters)
+        kpf = _iters_to(ctx.ll_trace(), target)
+        # timed runs
+        ctx.em_step(kp)
+        ts = []
+        for _ in range(3):
+            restart()
+            ts.append(_timed(stream, lambda: ctx.em_step(kp), reps=1))
+        t_plain = float(np.median(ts))
+        t_warm = t_ws = None
+        if kw is not None:
+            ctx.em_step(kw)
+            tw, tws = [], []
+            for _ in range(3):
+                restart()
+                tws.append(_timed(stream, lambda: ctx.warmstart(net), reps=1))
+                restart()
+                tw.append(_timed(stream, lambda: (ctx.warmstart(net), ctx.em_step(kw)), reps=1))
+            t_warm, t_ws = float(np.median(tw)), float(np.median(tws))
+        ctx.close()
+        rows.append(dict(id=seed0 + i, ll_star=llstar, k_plain=kp, k_warm=kw, k_heur=kh, k_perfect=kpf,
+                         taken=taken, ms_plain=t_plain, ms_warm=t_warm, ms_warmstart=t_ws))
+        if log and (i + 1) % 16 == 0:
+            log("measured %d/%d mixtures (%.1f s)" % (i + 1, n_eval, time.time() - t0))
+
+    def med(key):
+        a = np.array([r[key] if r[key] is not None else np.nan for r in rows], float)
+        return float(np.nanmedian(a)) if np.isfinite(a).any() else None
+
+    wp = np.array([r["ms_plain"] for r in rows], float)
+    ww = np.array([r["ms_warm"] if r["ms_warm"] is not None else np.inf for r in rows], float)
+    summary = {"mixtures": n_eval, "tol_nats_per_bin": TOL, "reference_iters": conv_iters,
+               "measured": "HIP events, end to end",
+               "plain_ms_median": med("ms_plain"), "warm_ms_median": float(np.median(ww)),
+               "warmstart_call_ms_median": med("ms_warmstart"),
+               "plain_iters_median": med("k_plain"), "warm_iters_median": med("k_warm"),
+               "whitening_only_iters_median": med("k_heur"), "perfect_net_iters_median": med("k_perfect"),
+               "warm_faster_frac": float(np.mean(ww < wp)),
+               "warm_reached_frac": float(np.mean([r["k_warm"] is not None for r in rows])),
+               "frequencies_kept_median": med("taken")}
+    return summary, rows
 
 
 def main(argv=None):
@@ -237,7 +201,6 @@ def main(argv=None):
     e.add_argument("--weights", required=True)
     e.add_argument("--n-eval", type=int, default=512)
     e.add_argument("--conv-iters", type=int, default=1500)
-    e.add_argument("--batch", type=int, default=32)
     e.add_argument("--out", default="")
     args = ap.parse_args(argv)
     {"train": cmd_train, "eval": cmd_eval}[args.cmd](args)
