@@ -477,6 +477,41 @@ typedef struct {
  */
 int fastfca_warmstart(fastfca_ctx *c, int b, const fastfca_net *net, int *n_taken);
 
+/* ====================================================================
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * ==================================================================== */
+
+/* Bytes of the fixed device array fastfca_fit_noalloc works in (one per GPU,
+ * held from the first call on that GPU until the process ends). */
+#define FASTFCA_NOALLOC_SCRATCH_BYTES (8u << 20)
+
+/*
+ * fastfca_fit_noalloc -- n_iter >= 1 iterations of Algorithm 1 (the same
+ * kernels and launch shape as fastfca_em_step on a context made by
+ * fastfca_init) on one mixture held in the caller's device buffers, with no
+ * device allocation, free, copy or memset:
+ *   x        [F][T][M] complex64, read in place (must be finite)
+ *   P        [F][M][M] complex128, lambda [F][N][M], v [F][T][N]: the start
+ *            on entry, updated in place (lambda, v > 0)
+ *   status   [F] int, output: 0, or FASTFCA_E_SINGULAR / FASTFCA_E_NONFINITE /
+ *            FASTFCA_E_DECREASE (the likelihood alarm at its default
+ *            tolerance, see fastfca_set_ll_alarm) for a frequency whose
+ *            iteration failed (its state is left where it stopped)
+ *   ll_trace [F][n_iter] double, output, or NULL: LL per bin of frequency f
+ *            after each iteration (eq:negll; the library's trace terms)
+ * The per-frequency work table, ln|det P|^2 and (when ll_trace is NULL) the
+ * trace live in the library's fixed device array: 256-byte aligned parts of
+ * 64 F, 8 F and 8 F n_iter bytes must fit in FASTFCA_NOALLOC_SCRATCH_BYTES
+ * (E_ARG otherwise; e.g. F = 513 allows n_iter <= 1900 without ll_trace).
+ * Every call on one GPU shares that array: calls that overlap on one GPU
+ * (on different streams or host threads) race. Shapes as fastfca_init
+ * (E_ARG, E_UNSUPPORTED). Asynchronous on hip_stream (NULL: the default
+ * stream); the error text of a rejected call is in fastfca_last_error(NULL).
+ */
+int fastfca_fit_noalloc(const fastfca_c64 *x, int F, int T, int M, int N, fastfca_c128 *P, float *lambda,
+                        float *v, int n_iter, int *status, double *ll_trace, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <string>
 #include <vector>
@@ -45,6 +46,11 @@ using namespace ffca;
 namespace {
 
 thread_local std::string g_init_error;
+// Error text of fastfca_fit_noalloc: a fixed buffer, so that a rejected call
+// allocates nothing either. fastfca_last_error(NULL) returns the newer of the
+// two messages.
+thread_local char g_noalloc_error[256];
+thread_local bool g_noalloc_error_newer = false;
 
 struct Problem {
     int F = 0, T = 0, M = 0, N = 0;  // T: bins of the iteration (frames, or blocks)
@@ -149,10 +155,12 @@ int set_err(fastfca_ctx *c, int code, const char *fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    if (c)
+    if (c) {
         c->err = buf;
-    else
+    } else {
         g_init_error = buf;
+        g_noalloc_error_newer = false;
+    }
     return code;
 }
 
@@ -644,6 +652,77 @@ bool valid_problem(fastfca_ctx *c, int b) { return c && b >= 0 && b < static_cas
 }  // namespace
 
 // ====================================================================== ABI
+// ------------------------------------------------------------------ allocation-free fit
+// Device memory of fastfca_fit_noalloc: the per-frequency work table, ln|det P|^2
+// and (when the caller passes no trace buffer) the likelihood trace. One copy
+// per GPU, kept until the process ends; host code reaches it only through the
+// per-device address taken with hipGetSymbolAddress (the array's name is a
+// host-side stand-in, not a device address).
+static __device__ __align__(256) unsigned char scratch[FASTFCA_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kNoallocMaxDevices = 64;
+void *g_scratch_ptr[kNoallocMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+int noalloc_err(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_noalloc_error, sizeof g_noalloc_error, fmt, ap);
+    va_end(ap);
+    g_noalloc_error_newer = true;
+    return code;
+}
+
+// Address of the scratch array on the current device, taken once per device.
+int scratch_address(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return noalloc_err(FASTFCA_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kNoallocMaxDevices) return noalloc_err(FASTFCA_E_HIP, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return noalloc_err(FASTFCA_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                               hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FASTFCA_OK;
+}
+
+// Work table of one mixture held in caller buffers; also clears its status.
+__global__ void noalloc_items_kernel(WorkItem *items, const float2 *x, double2 *P, float *lam, float *v,
+                                     double *trace, int trace_stride, double *ldet, int *status, int F, int T, int M,
+                                     int N) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    WorkItem w{};
+    w.x = x + static_cast<size_t>(f) * T * M;
+    w.z = nullptr;
+    w.v = v + static_cast<size_t>(f) * T * N;
+    w.lam = lam + static_cast<size_t>(f) * N * M;
+    w.P = P + static_cast<size_t>(f) * M * M;
+    w.ll_trace = trace + static_cast<size_t>(f) * trace_stride;
+    w.ldet = ldet + f;
+    w.status = status + f;
+    w.T = T;
+    w.M = M;
+    w.N = N;
+    w.B = 1;
+    w.Tx = T;
+    w.cls = 0;
+    items[f] = w;
+    status[f] = ST_OK;
+}
+
+constexpr size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+}  // namespace
+
 extern "C" {
 
 int fastfca_init(fastfca_ctx **out, const fastfca_c64 *x, int F, int T, int M, int N,
@@ -1155,8 +1234,46 @@ int fastfca_synth_mixture(fastfca_c64 *x, int F, int T, int M, int N, int rank, 
     return FASTFCA_OK;
 }
 
+int fastfca_fit_noalloc(const fastfca_c64 *x, int F, int T, int M, int N, fastfca_c128 *P, float *lambda,
+                        float *v, int n_iter, int *status, double *ll_trace, void *hip_stream) {
+    if (!x || !P || !lambda || !v || !status)
+        return noalloc_err(FASTFCA_E_ARG, "fit_noalloc: x, P, lambda, v and status are required");
+    if (F < 1 || T < 1 || M < 2 || N < 2 || T < M || n_iter < 1)
+        return noalloc_err(FASTFCA_E_ARG, "fit_noalloc: invalid F=%d T=%d M=%d N=%d n_iter=%d", F, T, M, N, n_iter);
+    ClassCfg cc{M, N, T};
+    if (M > FASTFCA_MAX_M || N > FASTFCA_MAX_N || T > FASTFCA_MAX_T || !pick_class(cc))
+        return noalloc_err(FASTFCA_E_UNSUPPORTED, "fit_noalloc: no compiled kernel for M=%d N=%d T=%d", M, N, T);
+    const size_t items_b = align256(sizeof(WorkItem) * static_cast<size_t>(F));
+    const size_t ldet_b = align256(sizeof(double) * static_cast<size_t>(F));
+    const size_t trace_b = ll_trace ? 0 : align256(sizeof(double) * static_cast<size_t>(F) * n_iter);
+    if (items_b + ldet_b + trace_b > FASTFCA_NOALLOC_SCRATCH_BYTES)
+        return noalloc_err(FASTFCA_E_ARG,
+                           "fit_noalloc: F=%d n_iter=%d needs %zu bytes of scratch, more than the %u available%s", F,
+                           n_iter, items_b + ldet_b + trace_b, FASTFCA_NOALLOC_SCRATCH_BYTES,
+                           ll_trace ? "" : " (pass ll_trace to keep the trace out of it)");
+    void *base = nullptr;
+    int rc = scratch_address(&base);
+    if (rc != FASTFCA_OK) return rc;
+    unsigned char *sp = static_cast<unsigned char *>(base);
+    WorkItem *items = reinterpret_cast<WorkItem *>(sp);
+    double *ldet = reinterpret_cast<double *>(sp + items_b);
+    double *trace = ll_trace ? ll_trace : reinterpret_cast<double *>(sp + items_b + ldet_b);
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    hipLaunchKernelGGL(noalloc_items_kernel, dim3((F + 255) / 256), dim3(256), 0, s, items,
+                       reinterpret_cast<const float2 *>(x), reinterpret_cast<double2 *>(P), lambda, v, trace, n_iter,
+                       ldet, status, F, T, M, N);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        const EmLaunch a{items, F, n_iter, nullptr, kAlgoEM, kDefaultLLAlarm};
+        e = cc.wide ? launch_em_wide(M, N, cc.bpt, cc.threads, a, F, s) : launch_em(M, N, cc.bpt, cc.threads, a, F, s);
+    }
+    if (e != hipSuccess) return noalloc_err(FASTFCA_E_HIP, "fit_noalloc: launch failed: %s", hipGetErrorString(e));
+    return FASTFCA_OK;
+}
+
 const char *fastfca_last_error(const fastfca_ctx *c) {
-    return c ? c->err.c_str() : g_init_error.c_str();
+    if (c) return c->err.c_str();
+    return g_noalloc_error_newer ? g_noalloc_error : g_init_error.c_str();
 }
 
 void fastfca_destroy(fastfca_ctx *c) {

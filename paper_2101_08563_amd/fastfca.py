@@ -68,6 +68,7 @@ SIGNATURES = {
     "fastfca_ws_targets": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _vp, _vp, _vp]),
     "fastfca_ws_apply": (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _vp, _vp]),
     "fastfca_warmstart": (_i, [_vp, _i, _vp, _pi]),
+    "fastfca_fit_noalloc": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _vp, _vp]),
 }
 
 
@@ -135,6 +136,26 @@ def synth_mixture(F, T, M, N, rank=8, diffuse=0.05, seed=0, stream=None, out=Non
     if rc != OK:
         raise FastFCAError(rc, lib.fastfca_last_error(None).decode())
     return x
+
+
+def fit_noalloc(x, P, lam, v, n_iter, status, ll_trace=None, stream=None):
+    """fastfca_fit_noalloc: n_iter IP+EM iterations on caller buffers with no
+    device allocation (x [F,T,M] complex64; P [F,M,M] complex128, lam [F,N,M]
+    and v [F,T,N] float32 updated in place; status [F] int32 and ll_trace
+    [F,n_iter] float64 (optional) written). Asynchronous on the stream."""
+    lib = load_library()
+    F, T, M = x.shape
+    N = lam.shape[1]
+    _check_dev(x, torch.complex64, (F, T, M), "x")
+    _check_dev(P, torch.complex128, (F, M, M), "P")
+    _check_dev(lam, torch.float32, (F, N, M), "lam")
+    _check_dev(v, torch.float32, (F, T, N), "v")
+    _check_dev(status, torch.int32, (F,), "status")
+    _check_dev(ll_trace, torch.float64, (F, n_iter), "ll_trace")
+    rc = lib.fastfca_fit_noalloc(_ptr(x), F, T, M, N, _ptr(P), _ptr(lam), _ptr(v), int(n_iter), _ptr(status),
+                                 _ptr(ll_trace), _stream(stream))
+    if rc != OK:
+        raise FastFCAError(rc, lib.fastfca_last_error(None).decode())
 
 
 class FastFCA:

@@ -58,3 +58,23 @@ def test_invalid_shapes_rejected_before_any_gpu_work():
     rc = lib.fastfca_init(ctypes.byref(ctx), None, 4, 100, 2, 3, None, None, None, 0, None)
     assert rc == fastfca.E_ARG
     assert b"NULL" in lib.fastfca_last_error(None)
+
+
+def test_noalloc_entry_point_rejects_before_any_gpu_work():
+    """fastfca_fit_noalloc validates its arguments and the size of its fixed
+    device array on the host, before any HIP call."""
+    from paper_2101_08563_amd import fastfca
+    if not os.path.exists(fastfca.LIB_PATH):
+        pytest.skip("libfastfca.so not built")
+    lib = fastfca.load_library()
+    p = ctypes.c_void_p(256)
+    # missing status
+    assert lib.fastfca_fit_noalloc(p, 9, 100, 2, 3, p, p, p, 5, None, None, None) == fastfca.E_ARG
+    # T < M, n_iter < 1
+    assert lib.fastfca_fit_noalloc(p, 9, 1, 2, 3, p, p, p, 5, p, None, None) == fastfca.E_ARG
+    assert lib.fastfca_fit_noalloc(p, 9, 100, 2, 3, p, p, p, 0, p, None, None) == fastfca.E_ARG
+    # no compiled kernel
+    assert lib.fastfca_fit_noalloc(p, 9, 100, 9, 3, p, p, p, 5, p, None, None) == fastfca.E_UNSUPPORTED
+    # the trace would not fit in the fixed array: 9 frequencies x 200000 doubles
+    assert lib.fastfca_fit_noalloc(p, 9, 100, 2, 3, p, p, p, 200000, p, None, None) == fastfca.E_ARG
+    assert b"scratch" in lib.fastfca_last_error(None)
