@@ -137,7 +137,8 @@ hipError_t launch_em_wide(int M, int N, int bpt, int threads, const EmLaunch &a,
                           hipStream_t s) {
     EmFn fn = wide_fn(M, N, bpt);
     if (!fn) return hipErrorInvalidValue;
-    if (threads < 64 || (threads & 63) || threads * bpt > kWideMaxT) return hipErrorInvalidValue;
+    if (threads < 64 || (threads & 63) || threads * bpt > kWideMaxT || threads > wide_max_threads(bpt))
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(threads), 0, s, a);
     return hipGetLastError();
 }

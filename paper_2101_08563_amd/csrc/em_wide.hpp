@@ -1,25 +1,35 @@
 // FastFCA IP+EM iteration (Algorithm 1, Sec. IV-E) for wide arrays and long
 // frames: M <= 8 microphones, N <= 12 sources, T <= 4096 frames.
 //
-// One workgroup owns one frequency for every iteration of a call. Per-bin h_t
-// and U_t stay in registers (BPT bins per thread); x_t is read again from
+// One workgroup owns one frequency for every iteration of a call. Per bin,
+// h_t and U_t stay in registers (BPT bins per thread); x_t is read again from
 // global memory in the two passes that need it (weighted covariances, U),
-// because an M = 8, T = 4000 frequency (256 KB of x) does not fit on a CU
-// next to its h and U.
+// because an M = 8, T = 4000 frequency (256 KB of x) does not fit on a CU next
+// to its h and U.
 //
-//   A  sigma^2 and 1/sigma^2 (eq:sigmadef); the M weighted covariances Q_m
-//      (eq:wsampcov) as a dense contraction over the frequency's bins: each
-//      wavefront stages 64 bins (x_t, 1/sigma^2_t) in LDS and lane (r, c) of
-//      the wavefront accumulates the Hermitian parameter (r, c) of all M
-//      matrices (M^2 <= 64 lanes; smaller M use several lane groups on
-//      different bins); the log-likelihood terms of the previous iterate.
+//   A  sigma^2 = L H from the current L and H (eq:sigmadef) and 1/sigma^2;
+//      the M weighted covariances Q_m (eq:wsampcov) as a dense
+//      contraction over the frequency's bins: each wavefront stages 64 bins
+//      (x_t and 1/sigma^2_t) in LDS and lane (r, c, part) accumulates one
+//      Hermitian parameter of all M matrices. Every lane runs the same
+//      instructions: the imaginary part of x_r conj(x_c) is the real part of
+//      x_r conj(i x_c), so those lanes read x_c rotated by a select instead
+//      of taking a branch. Each 64-bin chunk is summed in single precision,
+//      the chunks and the waves in double precision.
 //   IP wave 0, double precision, one matrix element per lane: for
 //      m = 1..M, A = P^H Q_m, Gauss-Jordan elimination with partial pivoting
 //      on [A | e_m] (eq:ip1), normalization (eq:ip2); then ln|det P|^2.
 //   B  U_mt = |w_m^H x_t|^2 (eq:Udef).
-//   C  for n = 1..N in order: G_n, Phi_n, L[:,n] (T-reduction), H[n,:].
-//      Each wavefront keeps its own LDS copy of L so an update by one lane is
-//      seen by the rest of its wavefront without a workgroup barrier.
+//   C  for n = 1..N in order: with g = h_n l_nm / sigma^2_m (sigma^2 from the
+//      current L and H, sources before n already updated) the posterior power
+//      over h_n is e_m = l_nm (1 + g (U_m / sigma^2_m - 1)); L[:,n] is the
+//      T-mean of e (one reduction of M values and one workgroup barrier), then
+//      h_n <- h_n (1/M) sum_m e_m / l_nm,new. sigma^2 is formed again for every
+//      source rather than kept: at M = 8, N = 10 its 8 values per bin would
+//      not fit in registers next to h and U without spilling. Each wavefront
+//      keeps its own LDS copy of L, so an update is seen by the rest of its
+//      wavefront without a further barrier. The log-likelihood terms of the
+//      new iterate (eq:negll) close the phase, while its U is in registers.
 #pragma once
 
 #include "device.hpp"
@@ -31,19 +41,20 @@ namespace ffca {
 constexpr int kWideBins = 4096;  // largest T of the wide family (threads * BPT)
 constexpr int kWideMaxM = 8;
 constexpr int kWideMaxN = 12;
-constexpr int kWideWaves = 16;
+constexpr int kWideWaves = 8;    // at most 512 threads per workgroup
 constexpr double kWideLnPi = 1.1447298858494002;
 
 constexpr int kWideStage = 32768;  // floats of per-wavefront scratch (128 KB)
 
 struct WideSmem {
     // per-wavefront scratch, kWideStage / (number of waves) floats each:
-    // staged x (64 bins x M complex) and 1/sigma^2 or U (64 x M) in phases A
-    // and B, the wavefront's partial sums of the Q_m (64 M floats) after A,
-    // and the posterior powers Phi_n of its bins (64 BPT M floats) in C.
+    // phase A: staged x (64 bins x M complex), 1/sigma^2 (64 x M), and the
+    //          wavefront's double precision partial sums of the Q_m;
+    // phase B: staged x and U (64 x M);
+    // phase C: the posterior powers e of its bins ([BPT][M][64]).
     alignas(16) float stage[kWideStage];
     alignas(16) float red[2][kWideMaxM][kWideWaves];
-    alignas(16) double red_d[2][kWideWaves];
+    alignas(16) double red_d[kWideWaves];
     float lamw[kWideWaves][kWideMaxN * kWideMaxM];
     double qtot[kWideMaxM * kWideMaxM * kWideMaxM];
     double2 Pd[kWideMaxM * kWideMaxM];
@@ -52,12 +63,29 @@ struct WideSmem {
     int flag;
 };
 
+// Floats of per-wavefront scratch a launch needs: phase A's staging and
+// double precision partials, or phase C's posterior powers.
+template <int M, int BPT>
+constexpr int wide_region_floats() {
+    constexpr int a = 64 * M * 3 + 2 * (64 / (M * M)) * M * M * M;
+    constexpr int c = BPT * M * 64;
+    return a > c ? a : c;
+}
+
+// x_t of bin t (zero for a bin past the end).
+template <int M>
+__device__ __forceinline__ void load_bins(const float2 *x, int t, bool valid, float2 (&out)[M]) {
+#pragma unroll
+    for (int r = 0; r < M; ++r) out[r] = valid ? x[t * M + r] : make_float2(0.f, 0.f);
+}
+
 template <int M, int N, int BPT>
 __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, double alarm, WideSmem &sm) {
     constexpr int M2 = M * M;
     constexpr int G = 64 / M2;  // lane groups in the weighted-covariance pass
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
+    const int nw = nthr >> 6;
     const int lane = tid & 63;
     const int wid = tid >> 6;
     const int T = it.T;
@@ -66,13 +94,14 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, dou
 
     float vr[BPT][N];
     float U[BPT][M];
-    bool valid[BPT];
+    unsigned vmask = 0;  // bit k: bin tid + k * nthr exists
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {
         const int t = tid + k * nthr;
-        valid[k] = t < T;
+        const bool valid = t < T;
+        vmask |= valid ? (1u << k) : 0u;
 #pragma unroll
-        for (int n = 0; n < N; ++n) vr[k][n] = valid[k] ? it.v[t * N + n] : 1.0f;
+        for (int n = 0; n < N; ++n) vr[k][n] = valid ? it.v[t * N + n] : 1.0f;
 #pragma unroll
         for (int m = 0; m < M; ++m) U[k][m] = 0.0f;
     }
@@ -84,102 +113,105 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, dou
         sm.P32[tid] = make_float2(static_cast<float>(p.x), static_cast<float>(p.y));
     }
     for (int i = tid; i < 2 * kWideMaxM * kWideWaves; i += nthr) (&sm.red[0][0][0])[i] = 0.0f;
-    if (tid < 2 * kWideWaves) (&sm.red_d[0][0])[tid] = 0.0;
     if (tid == 0) sm.flag = ST_OK;
     __syncthreads();
 
-    // this lane's role in the weighted-covariance pass
+    // this lane's Hermitian parameter in the weighted-covariance pass:
+    // entry (er, ec); the diagonal |x_r|^2, then re and im of x_r conj(x_c)
     const int grp = lane / M2;
     const int e = lane % M2;
     const bool active = grp < G;
-    int er = 0, ec = 0, epart = 0;  // entry (r, c); part 0 = |x_r|^2, 1 = re, 2 = im
+    int er = 0, ec = 0;
+    bool rot = false;  // imaginary part: read x_c as i x_c
     if (e < M) {
         er = ec = e;
     } else {
         upper_pair<M>((e - M) >> 1, er, ec);
-        epart = 1 + ((e - M) & 1);
+        rot = ((e - M) & 1) != 0;
     }
-    const int region = kWideStage / (nthr >> 6);
+    const int region = kWideStage / nw;
     float *stg = sm.stage + wid * region;
-    float2 *xs = reinterpret_cast<float2 *>(stg);  // [64][M]
-    float *ws = stg + 64 * M * 2;                  // [64][M]
+    float2 *xs = reinterpret_cast<float2 *>(stg);               // [64][M]
+    float *ws = stg + 64 * M * 2;                               // [64][M]
+    double *qd = reinterpret_cast<double *>(stg + 64 * M * 3);  // [G][M][M2] partials of this wave
 
     double ldet_prev = 0.0;
     double ll_last = 0.0;  // LL of the previous iterate (wave 0)
-    double llp = 0.0;  // LL terms of the latest iterate (end of phase C)
+    double lterm = 0.0;    // this lane's ln sigma^2 + U / sigma^2 of the latest iterate
     int buf = 0;
     int status = ST_OK;
     for (int iter = 0; iter <= n_iter; ++iter) {
         const bool last = (iter == n_iter);
-        // ---------------- phase A
-        float acc[M];
+        // ---------------- phase A: sigma^2, Q_m. The x of the next group of
+        // bins is requested before the current group is processed.
+        if (!last && active) {
 #pragma unroll
-        for (int m = 0; m < M; ++m) acc[m] = 0.0f;
+            for (int m = 0; m < M; ++m) qd[(grp * M + m) * M2 + e] = 0.0;
+        }
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
-            const int t = tid + k * nthr;
+            const bool valid = (vmask >> k) & 1u;
+            int loff = 0;
+            asm volatile("" : "+v"(loff));
             float2 xk[M];
-#pragma unroll
-            for (int r = 0; r < M; ++r) xk[r] = valid[k] ? it.x[t * M + r] : make_float2(0.f, 0.f);
-            float w[M];
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                float s = 0.0f;
-#pragma unroll
-                for (int n = 0; n < N; ++n) s = fmaf(vr[k][n], lamw[n * M + m], s);
-                w[m] = rcp(s);
-                if (N > 6) __builtin_amdgcn_sched_barrier(0);
-            }
+            if (!last) load_bins<M>(it.x, tid + k * nthr, valid, xk);
             if (!last) {
 #pragma unroll
-                for (int r = 0; r < M; ++r) xs[lane * M + r] = xk[r];
+                for (int m = 0; m < M; ++m) {
+                    float s = 0.0f;
 #pragma unroll
-                for (int m = 0; m < M; ++m) ws[lane * M + m] = valid[k] ? w[m] : 0.0f;
+                    for (int n = 0; n < N; ++n) s = fmaf(vr[k][n], lamw[loff + n * M + m], s);
+                    ws[lane * M + m] = valid ? rcp(s) : 0.0f;
+                }
+#pragma unroll
+                for (int r = 0; r < M; ++r) xs[lane * M + r] = xk[r];
                 if (active) {
-#pragma unroll 2
+                    float acc[M];
+#pragma unroll
+                    for (int m = 0; m < M; ++m) acc[m] = 0.0f;
+#pragma unroll 4
                     for (int b = grp; b < 64; b += G) {
-                        const float2 xa = xs[b * M + er], xb = xs[b * M + ec];
-                        float z;
-                        if (epart == 0)
-                            z = fmaf(xa.x, xa.x, xa.y * xa.y);
-                        else if (epart == 1)
-                            z = fmaf(xa.x, xb.x, xa.y * xb.y);
-                        else
-                            z = fmaf(xa.y, xb.x, -xa.x * xb.y);
+                        const float2 xa = xs[b * M + er];
+                        const float2 xc = xs[b * M + ec];
+                        const float bx = rot ? -xc.y : xc.x;
+                        const float by = rot ? xc.x : xc.y;
+                        const float z = fmaf(xa.x, bx, xa.y * by);
                         const float *wb = ws + b * M;
 #pragma unroll
                         for (int m = 0; m < M; ++m) acc[m] = fmaf(z, wb[m], acc[m]);
                     }
+                    // the chunk's single precision sums, added in double precision
+#pragma unroll
+                    for (int m = 0; m < M; ++m) qd[(grp * M + m) * M2 + e] += static_cast<double>(acc[m]);
                 }
             }
             // keep the next bin's loads from being hoisted (register pressure)
             __builtin_amdgcn_sched_barrier(0);
         }
-        if (!last && active) {
-#pragma unroll
-            for (int m = 0; m < M; ++m) stg[(grp * M + m) * M2 + e] = acc[m];
-        }
+        asm volatile("" ::: "memory");  // phase boundary: no code motion across it (registers)
         {
-            const double l = wave_sum(llp);
-            if (lane == 0) sm.red_d[buf][wid] = l;
+            const double l = wave_sum(lterm);
+            if (lane == 0) sm.red_d[wid] = l;
         }
         __syncthreads();
         if (!last) {
-            const int nw = nthr >> 6;
+            // Q_m: the double precision partials of every wave and lane group, in order
             for (int j = tid; j < M * M2; j += nthr) {
-                float s = 0.0f;
-                for (int w = 0; w < nw; ++w)
+                double s = 0.0;
+                for (int w = 0; w < nw; ++w) {
+                    const double *p = reinterpret_cast<const double *>(sm.stage + w * region + 64 * M * 3);
 #pragma unroll
-                    for (int g = 0; g < G; ++g) s += sm.stage[w * region + g * M * M2 + j];
-                sm.qtot[j] = static_cast<double>(s) * invT;
+                    for (int g = 0; g < G; ++g) s += p[g * M * M2 + j];
+                }
+                sm.qtot[j] = s * invT;
             }
             __syncthreads();
         }
+        asm volatile("" ::: "memory");  // phase boundary: no code motion across it (registers)
         if (wid == 0) {
             if (iter > 0) {
                 double s = 0.0;
-#pragma unroll
-                for (int w = 0; w < kWideWaves; ++w) s += sm.red_d[buf][w];
+                for (int w = 0; w < nw; ++w) s += sm.red_d[w];
                 const double ll = ldet_prev - static_cast<double>(M) * kWideLnPi - s * invT;
                 if (lane == 0) it.ll_trace[iter - 1] = ll;
                 if (!(ll == ll) || ll == INFINITY || ll == -INFINITY)
@@ -198,8 +230,8 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, dou
         if (last) break;
         __syncthreads();
         status = sm.flag;
+        asm volatile("" ::: "memory");  // phase boundary: no code motion across it (registers)
         if (status != ST_OK) break;
-        buf ^= 1;
 
         // ---------------- phase B: U = |P^H x|^2, staged per wavefront: the
         // owner lanes put 64 bins' x in LDS, lane (slot, m) forms y_m for
@@ -212,12 +244,13 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, dou
 #pragma unroll
             for (int r = 0; r < M; ++r) pcol[r] = sm.P32[r * M + mb];
             float *us = stg + 64 * M * 2;  // [64][M]
+            float2 xn[M];
+            load_bins<M>(it.x, tid, vmask & 1u, xn);
 #pragma unroll
             for (int k = 0; k < BPT; ++k) {
-                const int t = tid + k * nthr;
 #pragma unroll
-                for (int r = 0; r < M; ++r)
-                    xs[lane * M + r] = valid[k] ? it.x[t * M + r] : make_float2(0.f, 0.f);
+                for (int r = 0; r < M; ++r) xs[lane * M + r] = xn[r];
+                if (k + 1 < BPT) load_bins<M>(it.x, tid + (k + 1) * nthr, (vmask >> (k + 1)) & 1u, xn);
                 if (slot < S) {
 #pragma unroll 2
                     for (int b = slot; b < 64; b += S) {
@@ -237,44 +270,43 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, dou
             }
         }
 
+        asm volatile("" ::: "memory");  // phase boundary: no code motion across it (registers)
         // ---------------- phase C: sources in order
 #pragma unroll 1
         for (int n = 0; n < N; ++n) {
-            float *phis = stg;  // [BPT][M][64], lane-contiguous
-            float part[M];
-            float vn[BPT], rv[BPT];
+            float *es = stg;  // [BPT][M][64], lane-contiguous
+            float vn[BPT];
 #pragma unroll
             for (int k = 0; k < BPT; ++k) {
-                // source n's power without a dynamically indexed register array
                 float a = 0.0f;
 #pragma unroll
                 for (int nn = 0; nn < N; ++nn) a = (nn == n) ? vr[k][nn] : a;
                 vn[k] = a;
-                rv[k] = valid[k] ? rcp(a) : 0.0f;
             }
+            float part[M];
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 float lc[N];
 #pragma unroll
                 for (int nn = 0; nn < N; ++nn) lc[nn] = lamw[nn * M + m];
-                const float ln_ = lamw[n * M + m];
+                const float lo = lamw[n * M + m];
                 float pm = 0.0f;
 #pragma unroll
                 for (int k = 0; k < BPT; ++k) {
                     float s = 0.0f;
 #pragma unroll
                     for (int nn = 0; nn < N; ++nn) s = fmaf(vr[k][nn], lc[nn], s);
-                    const float a = vn[k] * ln_;
-                    const float g = a * rcp(s);
-                    const float ph = fmaf(g * g, U[k][m], (1.0f - g) * a);
-                    phis[(k * M + m) * 64 + lane] = ph;
-                    pm = fmaf(ph, rv[k], pm);
+                    const float a = vn[k] * lo;
+                    const float w = rcp(s);
+                    const float r = fmaf(U[k][m], w, -1.0f);
+                    const float ek = fmaf(lo * (a * w), r, lo);
+                    es[(k * M + m) * 64 + lane] = ek;
+                    pm += ((vmask >> k) & 1u) ? ek : 0.0f;
                 }
                 part[m] = pm;
                 __builtin_amdgcn_sched_barrier(0);
             }
             {
-                // wave sums four values at a time, value 4g + r in row r
                 constexpr int NG = (M + 3) / 4;
                 float tot[NG];
                 wave_sums_rows<M>(part, tot);
@@ -285,63 +317,64 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, dou
                 }
             }
             __syncthreads();
-            float s16 = 0.0f;
+            float lmine = 0.0f;
             if (lane < M) {
                 const float *p = sm.red[buf][lane];
 #pragma unroll
-                for (int w = 0; w < kWideWaves; ++w) s16 += p[w];
-            }
-            float rl[M];
-            bool good = true;
-            float lnew_mine = 0.0f;
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                const float l = readlane_f(s16, m) * invTf;
-                good = good && (l > 0.0f) && (l < INFINITY);
-                rl[m] = rcp(l);
-                if (lane == m) lnew_mine = l;
+                for (int w = 0; w < kWideWaves; ++w) lmine += p[w];
+                lmine *= invTf;
             }
             buf ^= 1;
+            const bool good = __all(lane >= M || ((lmine > 0.0f) && (lmine < INFINITY)));
             if (!good) {
                 status = ST_NONFINITE;
                 break;
             }
-            if (lane < M) lamw[n * M + lane] = lnew_mine;
+            if (lane < M) lamw[n * M + lane] = lmine;
+            float s[BPT];
+#pragma unroll
+            for (int k = 0; k < BPT; ++k) s[k] = 0.0f;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const float c = rcp(readlane_f(lmine, m) * static_cast<float>(M));
+#pragma unroll
+                for (int k = 0; k < BPT; ++k) s[k] = fmaf(es[(k * M + m) * 64 + lane], c, s[k]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
 #pragma unroll
             for (int k = 0; k < BPT; ++k) {
-                float s = 0.0f;
-#pragma unroll
-                for (int m = 0; m < M; ++m) s = fmaf(phis[(k * M + m) * 64 + lane], rl[m], s);
-                const float vnew = valid[k] ? s * (1.0f / static_cast<float>(M)) : 1.0f;
+                const bool valid = (vmask >> k) & 1u;
+                const float vnew = valid ? vn[k] * s[k] : 1.0f;
 #pragma unroll
                 for (int nn = 0; nn < N; ++nn)
                     if (nn == n) vr[k][nn] = vnew;
-                __builtin_amdgcn_sched_barrier(0);
             }
         }
         if (status != ST_OK) break;
-        // log-likelihood terms of this iterate (eq:negll): final sigma^2, U
-        llp = 0.0;
+        // log-likelihood terms of the new iterate (eq:negll), reported in the
+        // next pass of phase A
+        lterm = 0.0;
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
-            float lacc = 0.0f;
+            float lg = 0.0f, uw = 0.0f;
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                float s = 0.0f;
+                float s2 = 0.0f;
 #pragma unroll
-                for (int n = 0; n < N; ++n) s = fmaf(vr[k][n], lamw[n * M + m], s);
-                lacc += ln_fast(s) + U[k][m] * rcp(s);
+                for (int nn = 0; nn < N; ++nn) s2 = fmaf(vr[k][nn], lamw[nn * M + m], s2);
+                lg += log2_fast(s2);
+                uw = fmaf(U[k][m], rcp(s2), uw);
             }
-            if (valid[k]) llp += static_cast<double>(lacc);
-            __builtin_amdgcn_sched_barrier(0);
+            if ((vmask >> k) & 1u)
+                lterm += static_cast<double>(lg) * static_cast<double>(kLn2f) + static_cast<double>(uw);
         }
-        if (status != ST_OK) break;
+        asm volatile("" ::: "memory");  // phase boundary: no code motion across it (registers)
     }
 
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {
         const int t = tid + k * nthr;
-        if (valid[k]) {
+        if ((vmask >> k) & 1u) {
 #pragma unroll
             for (int n = 0; n < N; ++n) it.v[t * N + n] = vr[k][n];
         }

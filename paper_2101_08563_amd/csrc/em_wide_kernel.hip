@@ -10,7 +10,9 @@
 namespace ffca {
 
 template <int M, int N, int BPT>
-__global__ void __launch_bounds__(kWideBins / BPT) em_wide_kernel(EmLaunch a) {
+__global__ void __launch_bounds__(wide_max_threads(BPT)) em_wide_kernel(EmLaunch a) {
+    static_assert(wide_max_threads(BPT) / 64 <= kWideWaves, "reduction slots per wave");
+    static_assert(wide_region_floats<M, BPT>() <= kWideStage / (wide_max_threads(BPT) / 64), "per-wave scratch");
     __shared__ WideSmem sm;
     const WorkItem &it = a.items[blockIdx.x];
     if (*it.status != ST_OK) return;

@@ -68,6 +68,9 @@ hipError_t launch_em_wide(int M, int N, int bpt, int threads, const EmLaunch &a,
                           hipStream_t s);
 bool em_wide_supported(int M, int N, int bpt);
 constexpr int kWideMaxT = 4096;
+constexpr int kWideMaxThreads = 512;  // workgroup size limit of the wide kernels
+// Workgroup size limit of a wide kernel with bpt bins per thread.
+constexpr int wide_max_threads(int bpt) { return kWideMaxT / bpt < kWideMaxThreads ? kWideMaxT / bpt : kWideMaxThreads; }
 
 // Persistent launch over a mixed list of work items (any supported (M, N) in
 // the batch class table), pulling items from a device counter.

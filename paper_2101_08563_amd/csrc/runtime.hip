@@ -256,7 +256,7 @@ bool pick_class(ClassCfg &cc) {
     cc.wide = !use_resident(cc.M, cc.N, cc.Tmax);
     if (!cc.wide) return pick_default(cc.M, cc.Tmax, cc.threads, cc.bpt);
     cc.bpt = 8;
-    cc.threads = threads_for(cc.Tmax, 8, kWideMaxT);
+    cc.threads = threads_for(cc.Tmax, 8, kWideMaxT);  // at most 512 (kWideMaxThreads)
     return cc.threads != 0 && em_wide_supported(cc.M, cc.N, 8);
 }
 
@@ -982,10 +982,10 @@ int fastfca_set_config(fastfca_ctx *c, int threads, int bins_per_thread) {
         if (!cc.wide && threads * bins_per_thread > kResidentBins)
             return set_err(c, FASTFCA_E_ARG, "threads*bins_per_thread=%d > 2048 for M=%d N=%d",
                            threads * bins_per_thread, cc.M, cc.N);
-        if (cc.wide && (threads * bins_per_thread > kWideMaxT ||
+        if (cc.wide && (threads * bins_per_thread > kWideMaxT || threads > wide_max_threads(bins_per_thread) ||
                         !em_wide_supported(cc.M, cc.N, bins_per_thread)))
             return set_err(c, FASTFCA_E_ARG, "M=%d N=%d T=%d: the wide kernels take 4 or 8 bins per "
-                           "thread and at most 4096 bins", cc.M, cc.N, cc.Tmax);
+                           "thread, at most 512 threads and at most 4096 bins", cc.M, cc.N, cc.Tmax);
     }
     if (c->persistent) {
         c->p_threads = threads;
@@ -1180,7 +1180,7 @@ int fastfca_autotune(fastfca_ctx *c, int n_iter, const char *cache_path) {
             float best = 1e30f;
             for (int bpt : {2, 4, 8, 16}) {
                 const int th = threads_for(cc.Tmax, bpt, cc.wide ? kWideMaxT : kResidentBins);
-                if (!th) continue;
+                if (!th || (cc.wide && th > wide_max_threads(bpt))) continue;
                 if (cc.wide ? !em_wide_supported(cc.M, cc.N, bpt) : !em_supported(cc.M, cc.N, bpt, cc.cov))
                     continue;
                 cc.threads = th;
