@@ -2,6 +2,8 @@
 
   python -m paper_2101_08563_amd.train_warmstart train --out W.npz [--n-train 2048 --fit-iters 1000
          --minutes 8 --batch 256]
+  python -m paper_2101_08563_amd.train_warmstart train-stream --out W.npz [--n-train 20000 --chunk 64
+         --epochs 1 --minutes 14 --batch 256 --channels 64 --layers 8]
   python -m paper_2101_08563_amd.train_warmstart eval --weights W.npz [--n-eval 512 --conv-iters 1500]
 
 Workload: M=2 microphones, N=3 sources, F=513 bins, T=1000 frames (the paper's
@@ -67,6 +69,30 @@ def cmd_train(args):
                     "n_train_mixtures": args.n_train, "fit_iters": args.fit_iters}))
 
 
+def cmd_train_stream(args):
+    """Training at the full size: n_train mixtures regenerated chunk by chunk
+    from their seeds, targets from converged fits (LL gain < 1e-7 nats/bin per
+    iteration, at most 2000 iterations)."""
+    torch.manual_seed(0)
+    net = ConvNet(M=M, N=N, C=args.channels, L=args.layers, seed=args.seed)
+    log("network: %d parameters (C=%d, L=%d)" % (net.n_params(), args.channels, args.layers))
+    t0 = time.time()
+    r = warmstart.train_stream(net, args.n_train, F, T, M, N, chunk=args.chunk, epochs=args.epochs,
+                               steps_per_chunk=args.steps_per_chunk, minutes=args.minutes, batch=args.batch,
+                               lr=args.lr, log=log, log_every=max(1, args.n_train // args.chunk // 40))
+    hist, fits = r["history"], r["fit_iters"]
+    meta = dict(n_train_mixtures=args.n_train, chunk=args.chunk, epochs=args.epochs, chunks_skipped=r["skipped"],
+                steps=hist[-1][0], steps_per_chunk=r["steps_per_chunk"], batch=args.batch, lr=args.lr,
+                n_params=net.n_params(), channels=args.channels, layers=args.layers,
+                fit_rule="IP+EM from the seeded start until the LL gain per iteration < 1e-7 nats/bin "
+                         "for every mixture of the chunk, at most 2000 iterations",
+                fit_iters_median=float(np.median(fits)), fit_iters_max=int(np.max(fits)),
+                loss_first=hist[0][1], loss_last=hist[-1][1], train_seconds=round(time.time() - t0, 1),
+                workload="M=%d N=%d F=%d T=%d, rank 8, diffuse 0.05, seeds 0..%d" % (M, N, F, T, args.n_train - 1))
+    net.save(args.out, meta=meta)
+    log(json.dumps(dict(trained=args.out, **meta)))
+
+
 def _iters_to(trace, target):
     idx = np.nonzero(trace >= target)[0]
     return int(idx[0]) + 1 if len(idx) else None
@@ -106,7 +132,10 @@ def measure(weights, n_eval=64, conv_iters=1500, seed0=10**6, log=None):
     stream, each the median of three repetitions from the same start:
       plain  em_step(k_plain)
       warm   fastfca_warmstart(net) (features, network, judge) + em_step(k_warm)
-    (the graph of each em_step length is captured before its timed runs)."""
+    (the graph of each em_step length is captured before its timed runs).
+    Also reported: the log-likelihood after the first iteration from either
+    start, and how far the warm fit ends above or below LL* after
+    conv_iters iterations (a different local optimum shows there)."""
     net = ConvNet.load(weights)
     stream = torch.cuda.current_stream()
     rows = []
@@ -127,7 +156,8 @@ def measure(weights, n_eval=64, conv_iters=1500, seed0=10**6, log=None):
         restart()
         taken = ctx.warmstart(net, count=True)
         ctx.em_step(conv_iters)
-        kw = _iters_to(ctx.ll_trace(), target)
+        tr_w = ctx.ll_trace()
+        kw = _iters_to(tr_w, target)
         restart()
         ctx.warmstart(None)
         ctx.em_step(conv_iters)
@@ -160,7 +190,9 @@ def measure(weights, n_eval=64, conv_iters=1500, seed0=10**6, log=None):
                 tw.append(_timed(stream, lambda: (ctx.warmstart(net), ctx.em_step(kw)), reps=1))
             t_warm, t_ws = float(np.median(tw)), float(np.median(tws))
         ctx.close()
-        rows.append(dict(id=seed0 + i, ll_star=llstar, k_plain=kp, k_warm=kw, k_heur=kh, k_perfect=kpf,
+        rows.append(dict(id=seed0 + i, ll_star=llstar, ll_first_plain=float(tr_p[0]), ll_first_warm=float(tr_w[0]),
+                         ll_end_warm_minus_star=float(tr_w[-1]) - llstar,
+                         k_plain=kp, k_warm=kw, k_heur=kh, k_perfect=kpf,
                          taken=taken, ms_plain=t_plain, ms_warm=t_warm, ms_warmstart=t_ws))
         if log and (i + 1) % 16 == 0:
             log("measured %d/%d mixtures (%.1f s)" % (i + 1, n_eval, time.time() - t0))
@@ -179,7 +211,9 @@ def measure(weights, n_eval=64, conv_iters=1500, seed0=10**6, log=None):
                "whitening_only_iters_median": med("k_heur"), "perfect_net_iters_median": med("k_perfect"),
                "warm_faster_frac": float(np.mean(ww < wp)),
                "warm_reached_frac": float(np.mean([r["k_warm"] is not None for r in rows])),
-               "frequencies_kept_median": med("taken")}
+               "frequencies_kept_median": med("taken"),
+               "ll_first_iter_plain_median": med("ll_first_plain"), "ll_first_iter_warm_median": med("ll_first_warm"),
+               "ll_end_warm_minus_star_median": med("ll_end_warm_minus_star")}
     return summary, rows
 
 
@@ -197,13 +231,25 @@ def main(argv=None):
     t.add_argument("--channels", type=int, default=64)
     t.add_argument("--layers", type=int, default=6)
     t.add_argument("--seed", type=int, default=0)
+    ts = sub.add_parser("train-stream")
+    ts.add_argument("--out", required=True)
+    ts.add_argument("--n-train", type=int, default=20000)
+    ts.add_argument("--chunk", type=int, default=64)
+    ts.add_argument("--epochs", type=int, default=1)
+    ts.add_argument("--steps-per-chunk", type=int, default=0)
+    ts.add_argument("--minutes", type=float, default=14.0)
+    ts.add_argument("--batch", type=int, default=256)
+    ts.add_argument("--lr", type=float, default=1e-3)
+    ts.add_argument("--channels", type=int, default=64)
+    ts.add_argument("--layers", type=int, default=8)
+    ts.add_argument("--seed", type=int, default=0)
     e = sub.add_parser("eval")
     e.add_argument("--weights", required=True)
     e.add_argument("--n-eval", type=int, default=512)
     e.add_argument("--conv-iters", type=int, default=1500)
     e.add_argument("--out", default="")
     args = ap.parse_args(argv)
-    {"train": cmd_train, "eval": cmd_eval}[args.cmd](args)
+    {"train": cmd_train, "train-stream": cmd_train_stream, "eval": cmd_eval}[args.cmd](args)
 
 
 if __name__ == "__main__":

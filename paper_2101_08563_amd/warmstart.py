@@ -102,8 +102,13 @@ class ConvNet:
         self.bl.copy_(torch.from_numpy(np.asarray(d["bl"], np.float32)))
         self.pack()
 
-    def save(self, path):
-        np.savez(path, **self.state_dict())
+    def save(self, path, meta=None):
+        """Weights, and provenance fields (meta: name -> value) stored as
+        prov_<name> string arrays."""
+        d = self.state_dict()
+        for k, v in (meta or {}).items():
+            d["prov_" + k] = np.array(str(v))
+        np.savez(path, **d)
 
     @classmethod
     def load(cls, path, stream=None):
@@ -315,6 +320,118 @@ def make_training_set(n_mix, F, T, M, N, fit_iters, seed0, batch=16, rank=8, dif
         if log and (a // batch) % 16 == 0:
             log("training set: %d/%d mixtures fitted (%.1f s)" % (min(n_mix, a + batch), n_mix, time.time() - t0))
     return torch.cat(feats), torch.cat(tvs), torch.cat(tls)
+
+
+def converged_fit(xs, N, seed, max_iters=2000, tol=1e-7, block=100):
+    """Batched IP+EM from the library's seeded start until every mixture's
+    log-likelihood per bin gains less than tol in one iteration, or max_iters
+    iterations; returns (context, iterations run)."""
+    ctx = FastFCA.from_batch([dict(x=x, N=N) for x in xs], seed=seed)
+    done = 0
+    try:
+        while done < max_iters:
+            ctx.em_step(block)
+            done += block
+            gains = [float(tr[-1] - tr[-2]) for tr in (ctx.ll_trace(b) for b in range(len(xs)))]
+            if max(gains) < tol:
+                break
+    except FastFCAError:
+        ctx.close()
+        raise
+    return ctx, done
+
+
+def chunk_training_set(seeds, F, T, M, N, rank=8, diffuse=0.05, max_iters=2000, tol=1e-7):
+    """Features and targets of the mixtures with the given seeds (drawn on the
+    GPU), from converged fits: (feat [n*F, M, T], tv [n*F, N, T], tl [n*F, N*M],
+    iterations of the fit)."""
+    xs = [synth_mixture(F, T, M, N, rank=rank, diffuse=diffuse, seed=s) for s in seeds]
+    ctx, iters = converged_fit(xs, N, seed=int(seeds[0]), max_iters=max_iters, tol=tol)
+    feats, tvs, tls = [], [], []
+    for b, x in enumerate(xs):
+        P, lam, v = ctx.get_params(b)
+        P0, feat = features(x)
+        tv, tl = targets(P, lam, v, P0)
+        feats.append(feat)
+        tvs.append(tv)
+        tls.append(tl)
+    ctx.close()
+    return torch.cat(feats), torch.cat(tvs), torch.cat(tls), iters
+
+
+def _sgd_steps(net, feat, tv, tl, n_steps, g, batch, lr_at, wl, it0):
+    n = feat.shape[0]
+    loss = None
+    for k in range(n_steps):
+        idx = torch.randint(0, n, (batch,), generator=g).to(feat.device)
+        f, a, b = feat[idx].contiguous(), tv[idx].contiguous(), tl[idx].contiguous()
+        lv, ll = net.forward(f)
+        loss, _, glv, gll = pit_loss(lv, a, ll, b, net.N, net.M, wl=wl)
+        net.zero_grad()
+        net.backward(glv, gll)
+        net.step(lr=lr_at(it0 + k + 1), grad_scale=1.0 / batch)
+    return float(loss.mean()) if loss is not None else float("nan")
+
+
+def train_stream(net, n_train, F, T, M, N, chunk=64, epochs=1, steps_per_chunk=0, minutes=0.0, batch=256,
+                 lr=1e-3, wl=0.5, seed=0, log=print, log_every=20, max_fit_iters=2000, tol=1e-7):
+    """AdamW over n_train generated mixtures (seeds 0..n_train-1) in chunks:
+    each chunk is drawn and fitted to convergence on the GPU, turned into
+    features and targets, trained on for steps_per_chunk minibatches of
+    sequences (frequencies) drawn from it, then discarded; no training set is
+    stored. With steps_per_chunk 0 it is sized from the first chunk's measured
+    fit and step times so that the run takes about `minutes`. The learning
+    rate follows a cosine decay over all steps. A chunk whose fit fails
+    (a singular or non-finite frequency) is skipped and counted.
+    Returns dict(history=[(step, loss)], fit_iters=[...], skipped=k, steps_per_chunk=s)."""
+    g = torch.Generator(device="cpu")
+    g.manual_seed(seed)
+    n_chunks = (n_train + chunk - 1) // chunk
+    hist, fit_iters = [], []
+    skipped = 0
+    total = [1]
+    it = 0
+    t0 = time.time()
+
+    def lr_at(k):
+        return lr * 0.5 * (1.0 + math.cos(math.pi * min(k, total[0]) / total[0]))
+
+    for ep in range(epochs):
+        order = torch.randperm(n_chunks, generator=g).tolist()
+        for ci, c in enumerate(order):
+            seeds = list(range(c * chunk, min(n_train, (c + 1) * chunk)))
+            tf = time.time()
+            try:
+                feat, tv, tl, fi = chunk_training_set(seeds, F, T, M, N, max_iters=max_fit_iters, tol=tol)
+            except FastFCAError as e:
+                skipped += 1
+                if log:
+                    log("chunk of seeds %d..%d skipped: %s" % (seeds[0], seeds[-1], e))
+                continue
+            torch.cuda.synchronize()
+            tf = time.time() - tf
+            fit_iters.append(fi)
+            if not steps_per_chunk:
+                # size the run from this chunk: fit time and the time of a few steps
+                ts = time.time()
+                _sgd_steps(net, feat, tv, tl, 4, g, batch, lambda k: 0.0, wl, 0)
+                torch.cuda.synchronize()
+                per_step = (time.time() - ts) / 4
+                budget = minutes * 60.0 - (time.time() - t0)
+                spc = int((budget / (epochs * n_chunks) - tf) / per_step)
+                steps_per_chunk = max(8, spc)
+                if log:
+                    log("fit of a chunk %.2f s, %.2f ms per step: %d steps per chunk"
+                        % (tf, per_step * 1e3, steps_per_chunk))
+            total[0] = epochs * n_chunks * steps_per_chunk
+            val = _sgd_steps(net, feat, tv, tl, steps_per_chunk, g, batch, lr_at, wl, it)
+            it += steps_per_chunk
+            hist.append((it, val))
+            if log and (ci % log_every == 0 or ci == n_chunks - 1):
+                log("epoch %d chunk %d/%d (fit %d iterations, %.2f s) step %d/%d loss %.4f (%.1f s)"
+                    % (ep, ci + 1, n_chunks, fi, tf, it, total[0], val, time.time() - t0))
+            del feat, tv, tl
+    return dict(history=hist, fit_iters=fit_iters, skipped=skipped, steps_per_chunk=steps_per_chunk)
 
 
 def train(net, feat, tv, tl, steps, batch=256, lr=1e-3, wl=0.5, seed=0, log=print, log_every=200):
