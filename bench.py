@@ -307,7 +307,7 @@ def time_to_converge(n_eval=64, conv_iters=1500):
     headline-shaped mixtures (paper_2101_08563_amd.train_warmstart.measure)."""
     import contextlib
 
-    weights = os.path.join(ROOT, "paper_2101_08563_amd", "data", "warmstart_c64l6.npz")
+    weights = os.path.join(ROOT, "paper_2101_08563_amd", "data", "warmstart_c64l8.npz")
     try:
         from paper_2101_08563_amd import train_warmstart
         with contextlib.redirect_stdout(sys.stderr):
