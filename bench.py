@@ -240,12 +240,15 @@ def main():
         "config": {"workload": "FastFCA IP+%s x%d + MWF, M=%d N=%d F=%d T=%d" % (args.algo.upper(), iters, M, N, F, T),
                    "M": M, "N": N, "F": F, "T": T, "iters": iters, "threads": threads,
                    "bins_per_thread": bpt, "ll_per_bin": ll},
-        "roofline": roofline_alu("em_kernel<%d,%d,%d> (IP+%s, state resident on chip)" % (M, N, bpt, args.algo.upper()),
+        "roofline": roofline_alu("em_kernel<%d,%d,%d> (IP+%s, state resident on chip); timed per em_step call: one "
+                                 "launch over the first F - r frequencies and, when F leaves a small remainder r over "
+                                 "the CUs, the last r in consecutive launches on a side stream (the tail split)"
+                                 % (M, N, bpt, args.algo.upper()),
                                  flops_per_bin(M, N) * F * T * iters, kernel_ops_per_bin(M, N, args.algo) * F * T * iters,
                                  em_ms * 1e-3, {(M, N): F * T}, iters,
                                  traffic=measured_traffic() if (iters == 100 and args.algo == "em") else None),
     }
-    out["roofline"]["em_ms_per_launch"] = em_ms
+    out["roofline"]["em_ms_per_call"] = em_ms
     out["roofline"]["hbm_algorithmic_bytes_per_launch"] = em_bytes_per_bin(M, N) * F * T
     if args.calib_copy:
         n = args.calib_copy * (1 << 20) // 4

@@ -277,6 +277,27 @@ int fastfca_set_algorithm(fastfca_ctx *c, int algo);
  */
 int fastfca_set_ll_alarm(fastfca_ctx *c, double tol);
 
+/*
+ * fastfca_set_tail_split -- schedule of a context whose items form one class
+ * (a single mixture, or a batch of equal shapes) in later fastfca_em_step
+ * calls. When the frequencies all fit on the GPU at once but their number is
+ * not a multiple of the compute-unit count, r = n mod CUs of the CUs carry
+ * one workgroup more than the rest for the whole call. The split runs the
+ * first n - r frequencies as one launch and the last r in consecutive
+ * launches of about n_iter / blocks iterations each, on a side stream and at
+ * the highest wave priority, so that the extra load is spread over several
+ * CUs. The iterations are the same (Algorithm 1 or 2, in order, state kept
+ * exactly between launches): results and the LL trace are bitwise those of
+ * the unsplit schedule; the likelihood alarm compares consecutive iterations
+ * within each launch.
+ *   blocks  -1 (default): automatic, min(8, n_iter / 10) blocks when the
+ *           shape qualifies (1 <= r <= CUs / 4, one round of workgroups,
+ *           at least 2 blocks); 0: never split; 1..1024: that many blocks
+ *           (at most n_iter) whenever the shape qualifies.
+ * Errors: FASTFCA_E_ARG for a NULL context or blocks outside -1..1024.
+ */
+int fastfca_set_tail_split(fastfca_ctx *c, int blocks);
+
 /* Schedule of a batch context's fastfca_em_step. */
 enum {
     FASTFCA_SCHEDULE_CLASSES = 0,    /* one launch per (M, N, T-bucket) class, workgroups sized to T */

@@ -10,9 +10,10 @@ namespace ffca {
 template <int M, int N, int BPT>
 __global__ void __launch_bounds__(kResidentBins / BPT) em_cov_kernel(EmLaunch a) {
     __shared__ EmSmem<M * M * M, 2 * N * M, wave_slots(BPT)> sm;
+    if (a.prio) __builtin_amdgcn_s_setprio(3);  // as em_kernel
     const WorkItem &it = a.items[blockIdx.x];
     if (*it.status != ST_OK) return;  // frozen after an earlier failure
-    em_item<M, N, BPT, true>(it, a.n_iter, a.algo, a.ll_alarm, sm);
+    em_item<M, N, BPT, true>(it, a.n_iter, a.algo, a.ll_alarm, a.trace_off, sm);
 }
 
 template <int M, int N>

@@ -278,7 +278,8 @@ __device__ __forceinline__ int ip_sweep_reg2(Smem &sm, const cd (&P)[4], const d
 // whose block covariance Xhat_j (M^2 real parameters, read from it.z) replaces
 // x_j x_j^H: Q_m takes Xhat_j / sigma^2 and U_mj = w_m^H Xhat_j w_m.
 template <int M, int N, int BPT, bool COV, class Smem>
-__device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo, double alarm, Smem &sm) {
+__device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo, double alarm, int trace_off,
+                                        Smem &sm) {
     constexpr int NQ = M * M * M;
     constexpr int M2 = M * M;
     const int tid = threadIdx.x;
@@ -349,7 +350,7 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
     __syncthreads();
 
     double ldet_prev = M == 2 ? 1.0 : 0.0;  // ln|det P|^2 (M = 2: |det P|^2) of the latest iterate (wave 0)
-    double *const ll_trace = it.ll_trace;
+    double *const ll_trace = it.ll_trace + trace_off;
     double ll_last = 0.0;  // LL of the previous iterate (likelihood wave)
     int buf = 0;
     int status = ST_OK;

@@ -14,9 +14,12 @@ template <int M, int N, int BPT>
 __global__ void __launch_bounds__(kResidentBins / BPT)
     __attribute__((amdgpu_waves_per_eu(M == 3 && BPT == 8 && N <= 5 ? 2 : 1))) em_kernel(EmLaunch a) {
     __shared__ EmSmem<M * M * M, 2 * N * M, wave_slots(BPT)> sm;
+    // the few frequencies a launch of its own runs next to a full grid get
+    // the SIMDs first, so that their chain of iterations keeps pace
+    if (a.prio) __builtin_amdgcn_s_setprio(3);
     const WorkItem &it = a.items[blockIdx.x];
     if (*it.status != ST_OK) return;  // frozen after an earlier failure
-    em_item<M, N, BPT, false>(it, a.n_iter, a.algo, a.ll_alarm, sm);
+    em_item<M, N, BPT, false>(it, a.n_iter, a.algo, a.ll_alarm, a.trace_off, sm);
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -59,6 +62,13 @@ bool em_supported(int M, int N, int bpt, bool cov) {
     return (cov ? em_cov_lookup(M, N, bpt) : em_lookup(M, N, bpt)) != nullptr;
 }
 
+int em_blocks_per_cu(int M, int N, int bpt, int threads, bool cov) {
+    EmFn fn = cov ? em_cov_lookup(M, N, bpt) : em_lookup(M, N, bpt);
+    int n = 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, 0) != hipSuccess) return 0;
+    return n;
+}
+
 // Persistent launch over a mixed batch: every workgroup pulls the next work
 // item (one frequency of one mixture, longest first) from a device counter
 // and runs it with the (M, N) instantiation it needs. The grid drains when
@@ -80,7 +90,7 @@ __global__ void __launch_bounds__(kResidentBins / BPT) em_persistent_kernel(EmLa
         if (*it.status != ST_OK) continue;
         switch (it.M * 16 + it.N) {
 #define FFCA_CASE(MM, NN) \
-    case MM * 16 + NN: em_item<MM, NN, BPT, false>(it, a.n_iter, a.algo, a.ll_alarm, sm); break;
+    case MM * 16 + NN: em_item<MM, NN, BPT, false>(it, a.n_iter, a.algo, a.ll_alarm, a.trace_off, sm); break;
             FFCA_PERSISTENT_CLASSES(FFCA_CASE)
 #undef FFCA_CASE
             default: break;

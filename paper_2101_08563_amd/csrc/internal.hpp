@@ -48,6 +48,9 @@ struct EmLaunch {
     int algo;               // kAlgoEM or kAlgoMM
     double ll_alarm;        // a frequency whose LL per bin falls by more than this between two
                             // iterations of a call is stopped with ST_DECREASE (+inf: never)
+    int trace_off;          // first trace entry this launch writes (a launch that continues a
+                            // call's iterations writes after the entries already written)
+    int prio;               // 1: the launch's waves take the highest issue priority on their SIMD
 };
 
 // Launch one EM kernel (Algorithm 1 for n_iter iterations) over `n_items`
@@ -56,6 +59,9 @@ struct EmLaunch {
 hipError_t launch_em(int M, int N, int bpt, int threads, const EmLaunch &a, int grid,
                      hipStream_t s, bool cov = false);
 bool em_supported(int M, int N, int bpt, bool cov = false);
+// Workgroups of the resident kernel (M, N, bpt) with `threads` threads that
+// one CU holds at once (0 if the kernel does not exist).
+int em_blocks_per_cu(int M, int N, int bpt, int threads, bool cov = false);
 using EmFn = void (*)(EmLaunch);
 EmFn em_cov_lookup(int M, int N, int bpt);
 

@@ -141,6 +141,8 @@ struct fastfca_ctx {
     int graph_n_iter = -1;
     int algo = kAlgoEM;
     double ll_alarm = kDefaultLLAlarm;  // fastfca_set_ll_alarm
+    int tail_split = -1;              // fastfca_set_tail_split: -1 automatic, 0 off, k > 0 blocks
+    int ncu = 0;                      // compute units of the device
     MnmfState *mn = nullptr;          // FastMNMF context
     WsScratch ws;                     // fastfca_warmstart workspace
     std::string err;
@@ -500,14 +502,17 @@ int create(fastfca_ctx **out, int B, const fastfca_problem *probs, uint64_t seed
     }
     if (rc == FASTFCA_OK) rc = build_items(c);
     if (rc == FASTFCA_OK) {
-        // batches: side streams for the class schedule (the default); the
-        // persistent queue is kept ready as the alternative the autotuner times
-        if (B > 1) {
+        // side streams: the class schedule of a batch (the default; the
+        // persistent queue is kept ready as the alternative the autotuner
+        // times) and the tail split of a single class
+        if (hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess)
+            c->ncu = 0;
+        {
             bool ok = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) == hipSuccess;
             for (int q = 0; q < fastfca_ctx::kSide && ok; ++q)
                 ok = hipStreamCreateWithFlags(&c->side[q], hipStreamNonBlocking) == hipSuccess &&
                      hipEventCreateWithFlags(&c->join[q], hipEventDisableTiming) == hipSuccess;
-            if (!ok) rc = set_err(c, FASTFCA_E_HIP, "could not create the side streams of a batch");
+            if (!ok) rc = set_err(c, FASTFCA_E_HIP, "could not create the side streams");
         }
         c->persistent = B > 1;
         if (c->persistent) {
@@ -578,6 +583,39 @@ int record_mnmf(fastfca_ctx *c, int n_iter) {
     return FASTFCA_OK;
 }
 
+// Tail split of a single class. A launch of n workgroups, all resident at
+// once, puts ceil(n / CUs) of them on some CUs and one fewer on the rest; a
+// remainder of r = n mod CUs workgroups makes r CUs carry one workgroup more
+// than the others for the whole call, and the call waits for them. The split
+// runs the first n - r items as one launch (an even load on every CU) and the
+// last r items in `blocks` consecutive launches of about n_iter / blocks
+// iterations each, on a side stream, at the highest wave priority: each block
+// lands on whichever CU takes it, so the extra load is spread over several
+// CUs, and the priority keeps the r frequencies' own chain of iterations as
+// fast as the rest. The state between blocks (P in double precision, L, H)
+// is stored exactly, so the results are bitwise those of one launch; the
+// likelihood alarm compares consecutive iterations within a block.
+struct TailPlan {
+    int r = 0;       // items in the tail (0: no split)
+    int blocks = 0;  // launches the tail's iterations are cut into
+};
+
+TailPlan tail_plan(const fastfca_ctx *c, const ClassCfg &cc, int n_iter) {
+    TailPlan t;
+    const int n = static_cast<int>(cc.items.size());
+    const int C = c->ncu;
+    if (c->tail_split == 0 || cc.wide || C <= 0 || !c->side[0]) return t;
+    const int base = n / C, r = n % C;
+    if (base < 1 || r < 1 || r > C / 4) return t;
+    if (em_blocks_per_cu(cc.M, cc.N, cc.bpt, cc.threads, cc.cov) < base + 1) return t;  // not one round
+    int k = c->tail_split > 0 ? c->tail_split : std::min(8, n_iter / 10);
+    k = std::min(k, n_iter);
+    if (k < 2) return t;
+    t.r = r;
+    t.blocks = k;
+    return t;
+}
+
 int record_em(fastfca_ctx *c, int n_iter) {
     if (c->mn) return record_mnmf(c, n_iter);
     if (c->persistent) {
@@ -596,6 +634,27 @@ int record_em(fastfca_ctx *c, int n_iter) {
         return static_cast<double>(cc.items.size()) * cc.Tmax * (cc.M + cc.N);
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    if (ncls == 1) {
+        const auto &cc = c->classes[0];
+        const TailPlan tp = tail_plan(c, cc, n_iter);
+        if (tp.r > 0) {
+            const int n = static_cast<int>(cc.items.size());
+            const WorkItem *items = c->d_items + c->class_first[0];
+            HIPCHK(c, hipEventRecord(c->fork, c->stream));
+            HIPCHK(c, hipStreamWaitEvent(c->side[0], c->fork, 0));
+            EmLaunch a{items, n - tp.r, n_iter, nullptr, c->algo, c->ll_alarm, 0, 0};
+            HIPCHK(c, launch_em(cc.M, cc.N, cc.bpt, cc.threads, a, n - tp.r, c->stream, cc.cov));
+            for (int j = 0; j < tp.blocks; ++j) {
+                const int i0 = static_cast<int>(static_cast<long>(n_iter) * j / tp.blocks);
+                const int i1 = static_cast<int>(static_cast<long>(n_iter) * (j + 1) / tp.blocks);
+                EmLaunch b{items + (n - tp.r), tp.r, i1 - i0, nullptr, c->algo, c->ll_alarm, i0, 1};
+                HIPCHK(c, launch_em(cc.M, cc.N, cc.bpt, cc.threads, b, tp.r, c->side[0], cc.cov));
+            }
+            HIPCHK(c, hipEventRecord(c->join[0], c->side[0]));
+            HIPCHK(c, hipStreamWaitEvent(c->stream, c->join[0], 0));
+            return FASTFCA_OK;
+        }
+    }
     const int nstreams = (ncls > 1 && c->side[0]) ? 1 + fastfca_ctx::kSide : 1;
     if (nstreams > 1) {
         HIPCHK(c, hipEventRecord(c->fork, c->stream));
@@ -1005,6 +1064,15 @@ int fastfca_set_ll_alarm(fastfca_ctx *c, double tol) {
     if (tol != tol) return set_err(c, FASTFCA_E_ARG, "ll alarm tolerance is NaN");
     if (tol != c->ll_alarm) drop_graph(c);
     c->ll_alarm = tol;
+    return FASTFCA_OK;
+}
+
+int fastfca_set_tail_split(fastfca_ctx *c, int blocks) {
+    if (!c) return FASTFCA_E_ARG;
+    if (blocks < -1 || blocks > 1024)
+        return set_err(c, FASTFCA_E_ARG, "tail split %d: -1 (automatic), 0 (off) or 1..1024 blocks", blocks);
+    if (blocks != c->tail_split) drop_graph(c);
+    c->tail_split = blocks;
     return FASTFCA_OK;
 }
 

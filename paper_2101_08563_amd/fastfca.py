@@ -40,6 +40,7 @@ SIGNATURES = {
     "fastfca_get_config": (_i, [_vp, _i, _pi, _pi]),
     "fastfca_set_algorithm": (_i, [_vp, _i]),
     "fastfca_set_ll_alarm": (_i, [_vp, _d]),
+    "fastfca_set_tail_split": (_i, [_vp, _i]),
     "fastfca_set_schedule": (_i, [_vp, _i]),
     "fastfca_init_blocks": (_i, [ctypes.POINTER(_vp), _vp, _i, _i, _i, _i, _i, _vp, _vp, _vp, _u64, _vp]),
     "fastfca_block_length": (_i, [_vp, _i]),
@@ -340,6 +341,10 @@ class FastFCA:
         self._chk(self._lib.fastfca_warmstart(self._ctx, b, ctypes.byref(desc) if desc is not None else None,
                                               ctypes.byref(n) if count else None))
         return n.value if count else None
+
+    def set_tail_split(self, blocks=-1):
+        """fastfca_set_tail_split: -1 automatic, 0 off, k > 0 blocks."""
+        self._chk(self._lib.fastfca_set_tail_split(self._ctx, int(blocks)))
 
     def set_ll_alarm(self, tol):
         """fastfca_set_ll_alarm (float('inf') disables the alarm)."""
