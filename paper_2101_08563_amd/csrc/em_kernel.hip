@@ -10,13 +10,16 @@ namespace ffca {
 // VGPRs (two waves per SIMD); at N = 5 that costs some spills and still runs
 // 26 % faster than one wave per SIMD at 275 VGPRs (513 frequencies,
 // T = 2000). More sources would spill too much.
-template <int M, int N, int BPT>
+// PRIO: the instance for the tail launches of the tail split, whose waves take
+// the highest issue priority on their SIMD so that the few frequencies they
+// run keep pace next to a full grid. A separate instance, because the
+// priority instruction in the common kernel changes its register allocation
+// (twice the spills at M = 3, N = 5, eight bins per thread).
+template <int M, int N, int BPT, bool PRIO>
 __global__ void __launch_bounds__(kResidentBins / BPT)
     __attribute__((amdgpu_waves_per_eu(M == 3 && BPT == 8 && N <= 5 ? 2 : 1))) em_kernel(EmLaunch a) {
     __shared__ EmSmem<M * M * M, 2 * N * M, wave_slots(BPT)> sm;
-    // the few frequencies a launch of its own runs next to a full grid get
-    // the SIMDs first, so that their chain of iterations keeps pace
-    if (a.prio) __builtin_amdgcn_s_setprio(3);
+    if constexpr (PRIO) __builtin_amdgcn_s_setprio(3);
     const WorkItem &it = a.items[blockIdx.x];
     if (*it.status != ST_OK) return;  // frozen after an earlier failure
     em_item<M, N, BPT, false>(it, a.n_iter, a.algo, a.ll_alarm, a.trace_off, sm);
@@ -26,12 +29,13 @@ __global__ void __launch_bounds__(kResidentBins / BPT)
 
 template <int M, int N>
 struct BptTable {
-    static EmFn get(int bpt) {
+    // tail instances (prio) exist for four and eight bins per thread
+    static EmFn get(int bpt, bool prio) {
         switch (bpt) {
-            case 2: return em_kernel<M, N, 2>;
-            case 4: return em_kernel<M, N, 4>;
-            case 8: return em_kernel<M, N, 8>;
-            case 16: return em_kernel<M, N, 16>;
+            case 2: return prio ? nullptr : em_kernel<M, N, 2, false>;
+            case 4: return prio ? em_kernel<M, N, 4, true> : em_kernel<M, N, 4, false>;
+            case 8: return prio ? em_kernel<M, N, 8, true> : em_kernel<M, N, 8, false>;
+            case 16: return prio ? nullptr : em_kernel<M, N, 16, false>;
             default: return nullptr;
         }
     }
@@ -39,17 +43,17 @@ struct BptTable {
 
 #define FFCA_N_CASES(M)                      \
     switch (N) {                             \
-        case 2: return BptTable<M, 2>::get(bpt); \
-        case 3: return BptTable<M, 3>::get(bpt); \
-        case 4: return BptTable<M, 4>::get(bpt); \
-        case 5: return BptTable<M, 5>::get(bpt); \
-        case 6: return BptTable<M, 6>::get(bpt); \
-        case 7: return BptTable<M, 7>::get(bpt); \
-        case 8: return BptTable<M, 8>::get(bpt); \
+        case 2: return BptTable<M, 2>::get(bpt, prio); \
+        case 3: return BptTable<M, 3>::get(bpt, prio); \
+        case 4: return BptTable<M, 4>::get(bpt, prio); \
+        case 5: return BptTable<M, 5>::get(bpt, prio); \
+        case 6: return BptTable<M, 6>::get(bpt, prio); \
+        case 7: return BptTable<M, 7>::get(bpt, prio); \
+        case 8: return BptTable<M, 8>::get(bpt, prio); \
         default: return nullptr;             \
     }
 
-static EmFn em_lookup(int M, int N, int bpt) {
+static EmFn em_lookup(int M, int N, int bpt, bool prio = false) {
     switch (M) {
         case 2: FFCA_N_CASES(2)
         case 3: FFCA_N_CASES(3)
@@ -60,6 +64,10 @@ static EmFn em_lookup(int M, int N, int bpt) {
 
 bool em_supported(int M, int N, int bpt, bool cov) {
     return (cov ? em_cov_lookup(M, N, bpt) : em_lookup(M, N, bpt)) != nullptr;
+}
+
+bool em_tail_supported(int M, int N, int bpt, bool cov) {
+    return (cov ? em_cov_lookup(M, N, bpt, true) : em_lookup(M, N, bpt, true)) != nullptr;
 }
 
 int em_blocks_per_cu(int M, int N, int bpt, int threads, bool cov) {
@@ -120,32 +128,41 @@ hipError_t launch_em_persistent(const EmLaunch &a, int threads, int bpt, int gri
 }
 
 // ------------------------------------------------------------------ wide family
-template <> void (*wide_lookup<2>(int, int))(EmLaunch);
-template <> void (*wide_lookup<3>(int, int))(EmLaunch);
-template <> void (*wide_lookup<4>(int, int))(EmLaunch);
-template <> void (*wide_lookup<5>(int, int))(EmLaunch);
-template <> void (*wide_lookup<6>(int, int))(EmLaunch);
-template <> void (*wide_lookup<7>(int, int))(EmLaunch);
-template <> void (*wide_lookup<8>(int, int))(EmLaunch);
+template <> void (*wide_lookup<2>(int, int, bool))(EmLaunch);
+template <> void (*wide_lookup<3>(int, int, bool))(EmLaunch);
+template <> void (*wide_lookup<4>(int, int, bool))(EmLaunch);
+template <> void (*wide_lookup<5>(int, int, bool))(EmLaunch);
+template <> void (*wide_lookup<6>(int, int, bool))(EmLaunch);
+template <> void (*wide_lookup<7>(int, int, bool))(EmLaunch);
+template <> void (*wide_lookup<8>(int, int, bool))(EmLaunch);
 
-static EmFn wide_fn(int M, int N, int bpt) {
+static EmFn wide_fn(int M, int N, int bpt, bool prio = false) {
     switch (M) {
-        case 2: return wide_lookup<2>(N, bpt);
-        case 3: return wide_lookup<3>(N, bpt);
-        case 4: return wide_lookup<4>(N, bpt);
-        case 5: return wide_lookup<5>(N, bpt);
-        case 6: return wide_lookup<6>(N, bpt);
-        case 7: return wide_lookup<7>(N, bpt);
-        case 8: return wide_lookup<8>(N, bpt);
+        case 2: return wide_lookup<2>(N, bpt, prio);
+        case 3: return wide_lookup<3>(N, bpt, prio);
+        case 4: return wide_lookup<4>(N, bpt, prio);
+        case 5: return wide_lookup<5>(N, bpt, prio);
+        case 6: return wide_lookup<6>(N, bpt, prio);
+        case 7: return wide_lookup<7>(N, bpt, prio);
+        case 8: return wide_lookup<8>(N, bpt, prio);
         default: return nullptr;
     }
 }
 
 bool em_wide_supported(int M, int N, int bpt) { return wide_fn(M, N, bpt) != nullptr; }
 
+bool em_wide_tail_supported(int M, int N, int bpt) { return wide_fn(M, N, bpt, true) != nullptr; }
+
+int em_wide_blocks_per_cu(int M, int N, int bpt, int threads) {
+    EmFn fn = wide_fn(M, N, bpt);
+    int n = 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, 0) != hipSuccess) return 0;
+    return n;
+}
+
 hipError_t launch_em_wide(int M, int N, int bpt, int threads, const EmLaunch &a, int grid,
                           hipStream_t s) {
-    EmFn fn = wide_fn(M, N, bpt);
+    EmFn fn = wide_fn(M, N, bpt, a.prio != 0);
     if (!fn) return hipErrorInvalidValue;
     if (threads < 64 || (threads & 63) || threads * bpt > kWideMaxT || threads > wide_max_threads(bpt))
         return hipErrorInvalidValue;
@@ -155,7 +172,7 @@ hipError_t launch_em_wide(int M, int N, int bpt, int threads, const EmLaunch &a,
 
 hipError_t launch_em(int M, int N, int bpt, int threads, const EmLaunch &a, int grid,
                      hipStream_t s, bool cov) {
-    EmFn fn = cov ? em_cov_lookup(M, N, bpt) : em_lookup(M, N, bpt);
+    EmFn fn = cov ? em_cov_lookup(M, N, bpt, a.prio != 0) : em_lookup(M, N, bpt, a.prio != 0);
     if (!fn) return hipErrorInvalidValue;
     if (threads < 64 || threads * bpt > kResidentBins || (threads & 63)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(threads), 0, s, a);

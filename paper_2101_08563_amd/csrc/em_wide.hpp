@@ -80,7 +80,8 @@ __device__ __forceinline__ void load_bins(const float2 *x, int t, bool valid, fl
 }
 
 template <int M, int N, int BPT>
-__device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, double alarm, WideSmem &sm) {
+__device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, double alarm, int trace_off,
+                                             WideSmem &sm) {
     constexpr int M2 = M * M;
     constexpr int G = 64 / M2;  // lane groups in the weighted-covariance pass
     const int tid = threadIdx.x;
@@ -213,7 +214,7 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, dou
                 double s = 0.0;
                 for (int w = 0; w < nw; ++w) s += sm.red_d[w];
                 const double ll = ldet_prev - static_cast<double>(M) * kWideLnPi - s * invT;
-                if (lane == 0) it.ll_trace[iter - 1] = ll;
+                if (lane == 0) it.ll_trace[trace_off + iter - 1] = ll;
                 if (!(ll == ll) || ll == INFINITY || ll == -INFINITY)
                     status = ST_NONFINITE;
                 else if (iter > 1 && ll < ll_last - alarm)  // Algorithm 1 never lowers it

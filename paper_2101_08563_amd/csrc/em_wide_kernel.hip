@@ -9,42 +9,45 @@
 
 namespace ffca {
 
-template <int M, int N, int BPT>
+// PRIO: the tail instance of the tail split (see em_kernel.hip), at eight
+// bins per thread only.
+template <int M, int N, int BPT, bool PRIO>
 __global__ void __launch_bounds__(wide_max_threads(BPT)) em_wide_kernel(EmLaunch a) {
     static_assert(wide_max_threads(BPT) / 64 <= kWideWaves, "reduction slots per wave");
     static_assert(wide_region_floats<M, BPT>() <= kWideStage / (wide_max_threads(BPT) / 64), "per-wave scratch");
     __shared__ WideSmem sm;
+    if constexpr (PRIO) __builtin_amdgcn_s_setprio(3);
     const WorkItem &it = a.items[blockIdx.x];
     if (*it.status != ST_OK) return;
-    em_wide_item<M, N, BPT>(it, a.n_iter, a.ll_alarm, sm);
+    em_wide_item<M, N, BPT>(it, a.n_iter, a.ll_alarm, a.trace_off, sm);
 }
 
 using WideFn = void (*)(EmLaunch);
 
 template <int M, int N>
-static WideFn wide_bpt(int bpt) {
+static WideFn wide_bpt(int bpt, bool prio) {
     switch (bpt) {
-        case 4: return em_wide_kernel<M, N, 4>;
-        case 8: return em_wide_kernel<M, N, 8>;
+        case 4: return prio ? nullptr : em_wide_kernel<M, N, 4, false>;
+        case 8: return prio ? em_wide_kernel<M, N, 8, true> : em_wide_kernel<M, N, 8, false>;
         default: return nullptr;
     }
 }
 
 template <>
-void (*wide_lookup<FFCA_WIDE_M>(int N, int bpt))(EmLaunch) {
+void (*wide_lookup<FFCA_WIDE_M>(int N, int bpt, bool prio))(EmLaunch) {
     constexpr int M = FFCA_WIDE_M;
     switch (N) {
-        case 2: return wide_bpt<M, 2>(bpt);
-        case 3: return wide_bpt<M, 3>(bpt);
-        case 4: return wide_bpt<M, 4>(bpt);
-        case 5: return wide_bpt<M, 5>(bpt);
-        case 6: return wide_bpt<M, 6>(bpt);
-        case 7: return wide_bpt<M, 7>(bpt);
-        case 8: return wide_bpt<M, 8>(bpt);
-        case 9: return wide_bpt<M, 9>(bpt);
-        case 10: return wide_bpt<M, 10>(bpt);
-        case 11: return wide_bpt<M, 11>(bpt);
-        case 12: return wide_bpt<M, 12>(bpt);
+        case 2: return wide_bpt<M, 2>(bpt, prio);
+        case 3: return wide_bpt<M, 3>(bpt, prio);
+        case 4: return wide_bpt<M, 4>(bpt, prio);
+        case 5: return wide_bpt<M, 5>(bpt, prio);
+        case 6: return wide_bpt<M, 6>(bpt, prio);
+        case 7: return wide_bpt<M, 7>(bpt, prio);
+        case 8: return wide_bpt<M, 8>(bpt, prio);
+        case 9: return wide_bpt<M, 9>(bpt, prio);
+        case 10: return wide_bpt<M, 10>(bpt, prio);
+        case 11: return wide_bpt<M, 11>(bpt, prio);
+        case 12: return wide_bpt<M, 12>(bpt, prio);
         default: return nullptr;
     }
 }

@@ -50,7 +50,8 @@ struct EmLaunch {
                             // iterations of a call is stopped with ST_DECREASE (+inf: never)
     int trace_off;          // first trace entry this launch writes (a launch that continues a
                             // call's iterations writes after the entries already written)
-    int prio;               // 1: the launch's waves take the highest issue priority on their SIMD
+    int prio;               // 1: a tail launch, run by the kernels' tail instance (highest wave
+                            // issue priority on its SIMD)
 };
 
 // Launch one EM kernel (Algorithm 1 for n_iter iterations) over `n_items`
@@ -63,16 +64,20 @@ bool em_supported(int M, int N, int bpt, bool cov = false);
 // one CU holds at once (0 if the kernel does not exist).
 int em_blocks_per_cu(int M, int N, int bpt, int threads, bool cov = false);
 using EmFn = void (*)(EmLaunch);
-EmFn em_cov_lookup(int M, int N, int bpt);
+EmFn em_cov_lookup(int M, int N, int bpt, bool prio = false);
+// A tail instance (highest wave priority) exists for this shape.
+bool em_tail_supported(int M, int N, int bpt, bool cov = false);
 
 // Wide family (M <= 8, N <= 12, T <= kWideBins = 4096): x is re-read from
 // global memory each iteration; see em_wide.hpp. One lookup per M, defined in
 // the per-M translation units of em_wide_kernel.hip.
 template <int M>
-void (*wide_lookup(int N, int bpt))(EmLaunch);
+void (*wide_lookup(int N, int bpt, bool prio))(EmLaunch);
 hipError_t launch_em_wide(int M, int N, int bpt, int threads, const EmLaunch &a, int grid,
                           hipStream_t s);
 bool em_wide_supported(int M, int N, int bpt);
+int em_wide_blocks_per_cu(int M, int N, int bpt, int threads);
+bool em_wide_tail_supported(int M, int N, int bpt);
 constexpr int kWideMaxT = 4096;
 constexpr int kWideMaxThreads = 512;  // workgroup size limit of the wide kernels
 // Workgroup size limit of a wide kernel with bpt bins per thread.

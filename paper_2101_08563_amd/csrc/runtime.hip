@@ -583,18 +583,20 @@ int record_mnmf(fastfca_ctx *c, int n_iter) {
     return FASTFCA_OK;
 }
 
-// Tail split of a single class. A launch of n workgroups, all resident at
-// once, puts ceil(n / CUs) of them on some CUs and one fewer on the rest; a
-// remainder of r = n mod CUs workgroups makes r CUs carry one workgroup more
-// than the others for the whole call, and the call waits for them. The split
-// runs the first n - r items as one launch (an even load on every CU) and the
-// last r items in `blocks` consecutive launches of about n_iter / blocks
+// Tail split of a single class. Its n workgroups take the CUs in rounds of
+// S = CUs x (workgroups a CU holds at once). When they all fit in one round
+// (n <= S), a remainder of r = n mod CUs makes r CUs carry one workgroup more
+// than the others for the whole call; with several rounds, a last partial
+// round of r = n mod S workgroups runs alone. Either way the call waits for
+// those r frequencies. The split runs the first n - r items as one launch
+// and the last r in `blocks` consecutive launches of about n_iter / blocks
 // iterations each, on a side stream, at the highest wave priority: each block
-// lands on whichever CU takes it, so the extra load is spread over several
-// CUs, and the priority keeps the r frequencies' own chain of iterations as
-// fast as the rest. The state between blocks (P in double precision, L, H)
-// is stored exactly, so the results are bitwise those of one launch; the
-// likelihood alarm compares consecutive iterations within a block.
+// lands on whichever CU has room (with several rounds, in the gaps as the
+// rounds drain), so the extra load is spread thin over several CUs, and the
+// priority keeps the r frequencies' own chain of iterations as fast as the
+// rest. The state between blocks (P in double precision, L, H) is stored
+// exactly, so the results are bitwise those of one launch; the likelihood
+// alarm compares consecutive iterations within a block.
 struct TailPlan {
     int r = 0;       // items in the tail (0: no split)
     int blocks = 0;  // launches the tail's iterations are cut into
@@ -604,16 +606,32 @@ TailPlan tail_plan(const fastfca_ctx *c, const ClassCfg &cc, int n_iter) {
     TailPlan t;
     const int n = static_cast<int>(cc.items.size());
     const int C = c->ncu;
-    if (c->tail_split == 0 || cc.wide || C <= 0 || !c->side[0]) return t;
-    const int base = n / C, r = n % C;
-    if (base < 1 || r < 1 || r > C / 4) return t;
-    if (em_blocks_per_cu(cc.M, cc.N, cc.bpt, cc.threads, cc.cov) < base + 1) return t;  // not one round
+    if (c->tail_split == 0 || C <= 0 || !c->side[0]) return t;
+    if (!(cc.wide ? em_wide_tail_supported(cc.M, cc.N, cc.bpt) : em_tail_supported(cc.M, cc.N, cc.bpt, cc.cov)))
+        return t;
+    const int cap = cc.wide ? em_wide_blocks_per_cu(cc.M, cc.N, cc.bpt, cc.threads)
+                            : em_blocks_per_cu(cc.M, cc.N, cc.bpt, cc.threads, cc.cov);
+    if (cap < 1) return t;
+    const long S = static_cast<long>(C) * cap;
+    int r;
+    if (n <= S) {
+        r = n % C;
+        if (n < C || r < 1 || r > C / 4) return t;
+    } else {
+        r = static_cast<int>(n % S);
+        if (r < 1 || r > S / 4) return t;
+    }
     int k = c->tail_split > 0 ? c->tail_split : std::min(8, n_iter / 10);
     k = std::min(k, n_iter);
     if (k < 2) return t;
     t.r = r;
     t.blocks = k;
     return t;
+}
+
+hipError_t launch_class(const ClassCfg &cc, const EmLaunch &a, int grid, hipStream_t st) {
+    return cc.wide ? launch_em_wide(cc.M, cc.N, cc.bpt, cc.threads, a, grid, st)
+                   : launch_em(cc.M, cc.N, cc.bpt, cc.threads, a, grid, st, cc.cov);
 }
 
 int record_em(fastfca_ctx *c, int n_iter) {
@@ -643,12 +661,12 @@ int record_em(fastfca_ctx *c, int n_iter) {
             HIPCHK(c, hipEventRecord(c->fork, c->stream));
             HIPCHK(c, hipStreamWaitEvent(c->side[0], c->fork, 0));
             EmLaunch a{items, n - tp.r, n_iter, nullptr, c->algo, c->ll_alarm, 0, 0};
-            HIPCHK(c, launch_em(cc.M, cc.N, cc.bpt, cc.threads, a, n - tp.r, c->stream, cc.cov));
+            HIPCHK(c, launch_class(cc, a, n - tp.r, c->stream));
             for (int j = 0; j < tp.blocks; ++j) {
                 const int i0 = static_cast<int>(static_cast<long>(n_iter) * j / tp.blocks);
                 const int i1 = static_cast<int>(static_cast<long>(n_iter) * (j + 1) / tp.blocks);
                 EmLaunch b{items + (n - tp.r), tp.r, i1 - i0, nullptr, c->algo, c->ll_alarm, i0, 1};
-                HIPCHK(c, launch_em(cc.M, cc.N, cc.bpt, cc.threads, b, tp.r, c->side[0], cc.cov));
+                HIPCHK(c, launch_class(cc, b, tp.r, c->side[0]));
             }
             HIPCHK(c, hipEventRecord(c->join[0], c->side[0]));
             HIPCHK(c, hipStreamWaitEvent(c->stream, c->join[0], 0));

@@ -75,6 +75,18 @@ def test_split_with_algorithm_2():
     _same(_run(p, 30, -1, algo="mm"), _run(p, 30, 0, algo="mm"))
 
 
+@pytest.mark.parametrize("blocks", [-1, 5])
+def test_split_wide_family_partial_last_round(blocks):
+    """M = 8, N = 10, T = 4000 (one workgroup per CU): F = CUs + 1 leaves a
+    last round of one frequency, which the split spreads over the gaps."""
+    from paper_2101_08563_amd.fastfca import synth_mixture
+    F = _ncu() + 1
+    x = synth_mixture(F, 4000, 8, 10, rank=8, diffuse=0.05, seed=11)
+    print("wide F", F, "blocks", blocks, flush=True)
+    p = [(x, 10)]
+    _same(_run(p, 20, blocks), _run(p, 20, 0))
+
+
 def test_set_tail_split_rejects_bad_values():
     ctx = FastFCA(_mix(8, 64, 2, 2, 3), 2, seed=1)
     from paper_2101_08563_amd.fastfca import FastFCAError
