@@ -291,9 +291,13 @@ int fastfca_set_ll_alarm(fastfca_ctx *c, double tol);
  * the unsplit schedule; the likelihood alarm compares consecutive iterations
  * within each launch.
  *   blocks  -1 (default): automatic, min(8, n_iter / 10) blocks when the
- *           shape qualifies (1 <= r <= CUs / 4, one round of workgroups,
- *           at least 2 blocks); 0: never split; 1..1024: that many blocks
- *           (at most n_iter) whenever the shape qualifies.
+ *           shape qualifies and that makes at least 2; 0: never split;
+ *           1..1024: that many blocks (at most n_iter) whenever the shape
+ *           qualifies. The shape qualifies with one round of workgroups
+ *           when 1 <= r <= CUs / 4 and the extra workgroup adds a wave to
+ *           a SIMD of its CU (otherwise the CUs carrying it are no slower),
+ *           and with several rounds when the last round holds at most a
+ *           quarter of the slots.
  * Errors: FASTFCA_E_ARG for a NULL context or blocks outside -1..1024.
  */
 int fastfca_set_tail_split(fastfca_ctx *c, int blocks);

@@ -597,6 +597,8 @@ int record_mnmf(fastfca_ctx *c, int n_iter) {
 // rest. The state between blocks (P in double precision, L, H) is stored
 // exactly, so the results are bitwise those of one launch; the likelihood
 // alarm compares consecutive iterations within a block.
+constexpr int kSimdsPerCu = 4;
+
 struct TailPlan {
     int r = 0;       // items in the tail (0: no split)
     int blocks = 0;  // launches the tail's iterations are cut into
@@ -617,6 +619,11 @@ TailPlan tail_plan(const fastfca_ctx *c, const ClassCfg &cc, int n_iter) {
     if (n <= S) {
         r = n % C;
         if (n < C || r < 1 || r > C / 4) return t;
+        // the extra workgroup must add a wave to some SIMD of its CU, or the
+        // CUs that carry it are no slower than the rest (short frames: a
+        // workgroup of one wave per frequency)
+        const int W = (cc.threads + 63) / 64, base = n / C;
+        if ((base + 1) * W <= kSimdsPerCu * ((base * W + kSimdsPerCu - 1) / kSimdsPerCu)) return t;
     } else {
         r = static_cast<int>(n % S);
         if (r < 1 || r > S / 4) return t;

@@ -53,10 +53,11 @@ def _mix(F, T, M, N, mid):
 
 @pytest.mark.parametrize("blocks,n_iter", [(-1, 40), (3, 10), (7, 23)])
 def test_split_equals_one_launch_bitwise(blocks, n_iter):
-    """One remainder frequency (F = CUs + 1): automatic and forced block
-    counts, blocks of unequal length."""
+    """One remainder frequency (F = CUs + 1, four waves per workgroup, so the
+    split applies): automatic and forced block counts, blocks of unequal
+    length."""
     F = _ncu() + 1
-    p = [(_mix(F, 200, 2, 3, 0), 3)]
+    p = [(_mix(F, 1000, 2, 3, 0), 3)]
     print("F", F, "blocks", blocks, "iterations", n_iter, flush=True)
     _same(_run(p, n_iter, blocks), _run(p, n_iter, 0))
 
@@ -65,13 +66,13 @@ def test_split_batch_of_equal_shapes_and_resumed_calls():
     """Two mixtures of one shape (one class, remainder 2 items) and a call
     split into two em_step calls."""
     F = _ncu() // 2 + 1
-    p = [(_mix(F, 300, 3, 4, 1), 4), (_mix(F, 300, 3, 4, 2), 4)]
+    p = [(_mix(F, 1000, 3, 4, 1), 4), (_mix(F, 1000, 3, 4, 2), 4)]
     _same(_run(p, 30, -1, steps=[20, 30]), _run(p, 30, 0, steps=[20, 30]))
 
 
 def test_split_with_algorithm_2():
     F = _ncu() + 1
-    p = [(_mix(F, 200, 2, 3, 4), 3)]
+    p = [(_mix(F, 1000, 2, 3, 4), 3)]
     _same(_run(p, 30, -1, algo="mm"), _run(p, 30, 0, algo="mm"))
 
 
