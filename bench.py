@@ -133,6 +133,19 @@ def roofline_alu(kernel, flops_8d, ops_kernel, seconds, bins_by_shape, iters, tr
             "hbm_streaming_equivalent_frac_x_twice": twice}
 
 
+def calib_copy(mib):
+    """Three plain device copies of mib MiB (the reference for scaling the
+    rocprofv3 byte counters); returns the bytes one copy moves."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return 2 * n * 4
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,7 +178,10 @@ def main():
     single = {"batch": bench_batch, "large": bench_large, "batch32": bench_batch32, "blocks": bench_blocks,
               "mnmf": bench_mnmf}
     if args.workload in single:
-        print(json.dumps(single[args.workload](args)))
+        out = single[args.workload](args)
+        if args.calib_copy:
+            out["calib_copy_bytes"] = calib_copy(args.calib_copy)
+        print(json.dumps(out))
         return
 
     import torch
@@ -251,13 +267,7 @@ def main():
     out["roofline"]["em_ms_per_call"] = em_ms
     out["roofline"]["hbm_algorithmic_bytes_per_launch"] = em_bytes_per_bin(M, N) * F * T
     if args.calib_copy:
-        n = args.calib_copy * (1 << 20) // 4
-        a = torch.ones(n, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        out["calib_copy_bytes"] = 2 * n * 4
+        out["calib_copy_bytes"] = calib_copy(args.calib_copy)
 
     if not args.no_cpu:
         import oracle

@@ -282,6 +282,35 @@ __global__ void fill_int_kernel(int *p, int n, int value) {
     if (i < n) p[i] = value;
 }
 
+// fastfca_set_params in one launch: copy P, lambda and v (each optional) and
+// clear the frequencies' status. Grid-stride over 16-byte words when both
+// pointers of an array are 16-byte aligned, elements otherwise.
+template <typename T>
+__device__ __forceinline__ void copy_array(T *dst, const T *src, size_t n, size_t i0, size_t stride) {
+    if (!dst || !src) return;
+    const size_t bytes = n * sizeof(T);
+    if (((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15) == 0) {
+        const size_t n16 = bytes / 16;
+        float4 *d = reinterpret_cast<float4 *>(dst);
+        const float4 *s = reinterpret_cast<const float4 *>(src);
+        for (size_t i = i0; i < n16; i += stride) d[i] = s[i];
+        const size_t done = n16 * 16 / sizeof(T);
+        for (size_t i = done + i0; i < n; i += stride) dst[i] = src[i];
+    } else {
+        for (size_t i = i0; i < n; i += stride) dst[i] = src[i];
+    }
+}
+
+__global__ void set_params_kernel(double2 *P, const double2 *Ps, size_t nP, float *lam, const float *ls, size_t nl,
+                                  float *v, const float *vs, size_t nv, int *status, int F) {
+    const size_t i0 = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    copy_array(P, Ps, nP, i0, stride);
+    copy_array(lam, ls, nl, i0, stride);
+    copy_array(v, vs, nv, i0, stride);
+    for (size_t i = i0; i < static_cast<size_t>(F); i += stride) status[i] = ST_OK;
+}
+
 // SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): the k-th output of the stream
 // seeded with s is mix(s + (k + 1) * 0x9E3779B97F4A7C15).
 __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
@@ -400,6 +429,15 @@ hipError_t launch_check_positive(const float *a, size_t n, int *flag, hipStream_
 hipError_t launch_identity_P(double2 *P, int F, int M, hipStream_t s) {
     const size_t n = static_cast<size_t>(F) * M * M;
     hipLaunchKernelGGL(identity_P_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, P, F, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_params(double2 *P, const double2 *Ps, size_t nP, float *lam, const float *ls, size_t nl,
+                             float *v, const float *vs, size_t nv, int *status, int F, hipStream_t s) {
+    // enough 16-byte words in flight to stream v at full bandwidth; at most 2048 workgroups
+    const size_t words = (nv * sizeof(float) + 15) / 16 + static_cast<size_t>(F);
+    const int blocks = static_cast<int>(std::min<size_t>(2048, std::max<size_t>(1, (words + 255) / 256)));
+    hipLaunchKernelGGL(set_params_kernel, dim3(blocks), dim3(256), 0, s, P, Ps, nP, lam, ls, nl, v, vs, nv, status, F);
     return hipGetLastError();
 }
 

@@ -107,5 +107,9 @@ hipError_t launch_seeded_init(const float2 *x, const float *z, float *lam, float
 // Block covariances z [F][J][M*M] of x [F][J*B][M] (Sec. VI).
 hipError_t launch_block_cov(const float2 *x, float *z, int F, int J, int B, int M, hipStream_t s);
 hipError_t launch_fill_int(int *p, int n, int value, hipStream_t s);
+// Copy P [nP], lambda [nl] and v [nv] (a NULL source skips that array) and
+// set status[0..F) to ST_OK, in one launch.
+hipError_t launch_set_params(double2 *P, const double2 *Ps, size_t nP, float *lam, const float *ls, size_t nl,
+                             float *v, const float *vs, size_t nv, int *status, int F, hipStream_t s);
 
 }  // namespace ffca

@@ -1023,11 +1023,9 @@ int fastfca_set_params(fastfca_ctx *c, int b, const fastfca_c128 *P, const float
     if (!valid_problem(c, b)) return c ? set_err(c, FASTFCA_E_ARG, "bad mixture index %d", b) : FASTFCA_E_ARG;
     auto &p = c->probs[b];
     const size_t F = p.F, T = p.T, M = p.M, N = p.N;
-    if (P) HIPCHK(c, hipMemcpyAsync(p.P, P, sizeof(double2) * F * M * M, hipMemcpyDeviceToDevice, c->stream));
-    if (lambda)
-        HIPCHK(c, hipMemcpyAsync(p.lam, lambda, sizeof(float) * F * N * M, hipMemcpyDeviceToDevice, c->stream));
-    if (v) HIPCHK(c, hipMemcpyAsync(p.v, v, sizeof(float) * F * T * N, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, launch_fill_int(c->d_status + p.item0, p.F, ST_OK, c->stream));
+    // one launch for the three copies and the status reset
+    HIPCHK(c, launch_set_params(p.P, reinterpret_cast<const double2 *>(P), F * M * M, p.lam, lambda, F * N * M,
+                                p.v, v, F * T * N, c->d_status + p.item0, p.F, c->stream));
     return FASTFCA_OK;
 }
 
