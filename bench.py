@@ -91,7 +91,7 @@ def cpu_model():
     return "unknown"
 
 
-KERNEL_FILES = ["em_item.hpp", "em_kernel.hip", "device.hpp", "internal.hpp", "ip_sm.hpp", "ip_wave.hpp"]
+KERNEL_FILES = ["em_item.hpp", "em_kernel.hip", "device.hpp", "internal.hpp", "ip_sm.hpp", "ip_common.hpp"]
 
 
 def kernel_source_hash() -> str:

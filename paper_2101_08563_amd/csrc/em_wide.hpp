@@ -16,9 +16,11 @@
 //      x_r conj(i x_c), so those lanes read x_c rotated by a select instead
 //      of taking a branch. Each 64-bin chunk is summed in single precision,
 //      the chunks and the waves in double precision.
-//   IP wave 0, double precision, one matrix element per lane: for
-//      m = 1..M, A = P^H Q_m, Gauss-Jordan elimination with partial pivoting
-//      on [A | e_m] (eq:ip1), normalization (eq:ip2); then ln|det P|^2.
+//   IP wave 0, double precision (ip_inv.hpp): the inverses of the Q_m and of
+//      P from one Gauss-Jordan run, then for m = 1..M in order w_m from
+//      Q_m^{-1} and P^{-1} (eq:ip1, eq:ip2), P^{-1} and det P kept current by
+//      rank-one updates; the stage region, idle during the IP, holds its LDS
+//      work space.
 //   B  U_mt = |w_m^H x_t|^2 (eq:Udef).
 //   C  for n = 1..N in order: with g = h_n l_nm / sigma^2_m (sigma^2 from the
 //      current L and H, sources before n already updated) the posterior power
@@ -34,7 +36,7 @@
 
 #include "device.hpp"
 #include "internal.hpp"
-#include "ip_wave.hpp"
+#include "ip_inv.hpp"
 
 namespace ffca {
 
@@ -45,6 +47,7 @@ constexpr int kWideWaves = 8;    // at most 512 threads per workgroup
 constexpr double kWideLnPi = 1.1447298858494002;
 
 constexpr int kWideStage = 32768;  // floats of per-wavefront scratch (128 KB)
+static_assert(2 * ip_inv_scratch_doubles<kWideMaxM>() <= kWideStage, "IP scratch in the stage region");
 
 struct WideSmem {
     // per-wavefront scratch, kWideStage / (number of waves) floats each:
@@ -59,7 +62,6 @@ struct WideSmem {
     double qtot[kWideMaxM * kWideMaxM * kWideMaxM];
     double2 Pd[kWideMaxM * kWideMaxM];
     float2 P32[kWideMaxM * kWideMaxM];
-    IpLds<kWideMaxM> ip;
     int flag;
 };
 
@@ -223,7 +225,8 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, dou
             }
             if (!last && status == ST_OK) {
                 double ldet = 0.0;
-                status = ip_wave<M, kWideMaxM>(sm.qtot, sm.Pd, sm.P32, sm.ip, ldet);
+                // the stage region is idle while wave 0 runs the IP
+                status = ip_inv<M>(sm.qtot, sm.Pd, sm.P32, reinterpret_cast<double *>(sm.stage), ldet);
                 if (status == ST_OK) ldet_prev = ldet;
             }
             if (lane == 0) sm.flag = status;

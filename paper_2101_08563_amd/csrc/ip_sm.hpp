@@ -3,7 +3,7 @@
 
 #include "device.hpp"
 #include "internal.hpp"
-#include "ip_wave.hpp"
+#include "ip_common.hpp"
 
 namespace ffca {
 

@@ -95,9 +95,11 @@ def test_config1_headline_case_parity():
 
 
 @pytest.mark.parametrize("M,N,T", [(2, 2, 77), (2, 4, 300), (3, 4, 129), (3, 5, 640),
-                                   (4, 5, 257), (4, 6, 1000), (2, 8, 513), (4, 2, 65)])
+                                   (4, 5, 257), (4, 6, 1000), (2, 8, 513), (4, 2, 65),
+                                   (2, 8, 2048), (3, 5, 2048), (4, 6, 2047)])
 def test_classes_and_ragged_tails(M, N, T):
-    """Every (M, N) family, T not a multiple of the wavefront, several tiles."""
+    """Every (M, N) family, T not a multiple of the wavefront, several tiles,
+    and the largest frame count of the resident family (2048)."""
     x, P0, lam0, v0 = make_case(9, T, M, N, rank=3, diffuse=0.1, config_id=10 + M, mixture_id=N)
     g = run_gpu(x, P0, lam0, v0, 20)
     check_against_oracle(x, P0, lam0, v0, 20, g, "M%d N%d T%d" % (M, N, T))

@@ -49,7 +49,9 @@ def test_wide_family_parity(M, N, T):
     for k in ("v", "lam", "P", "y", "v_f", "lam_f", "P_f", "y_f"):
         assert errs[k] < 1e-4, (k, errs)
     assert errs["v_log999"] < 1e-3, errs
-    assert errs["ll"] < 1e-6 and errs["tr"] < 1e-4, errs
+    # the trace's per-bin terms are single precision logarithms; with up to
+    # eight channels per bin they stay within 2e-6 nats/bin (1.3e-6 observed)
+    assert errs["ll"] < 1e-6 and errs["tr"] < 2e-6, errs
 
 
 def test_wide_launch_shapes_agree():

@@ -85,9 +85,11 @@ def test_m2_closed_form_matches_oracle(seed):
     assert abs(lw - lo) <= 1e-11
 
 
-@pytest.mark.parametrize("M", [3, 4])
+@pytest.mark.parametrize("M", [3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("seed", range(4))
 def test_inverse_form_matches_oracle(M, seed):
+    """The form of the resident kernels' sweep for M = 3, 4 and of the wide
+    kernels' sweep for M up to 8."""
     rng = np.random.default_rng(100 + 10 * M + seed)
     Q = np.stack([hpd(rng, M) for _ in range(M)])
     P0 = np.eye(M, dtype=complex) if seed == 0 else general(rng, M)
