@@ -306,13 +306,19 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
     float mk[BPT];
     // M = 2 and M = 4 (four bins per thread) keep sigma^2 and 1/sigma^2 of
     // every bin from phase A through phase C: source 1 uses them as they are,
-    // and each later source updates sigma^2 by the change of its own term
-    // (two FMAs instead of N). Phase A recomputes them from L and H every
-    // iteration, so rounding does not accumulate across iterations. The
-    // other shapes would lose occupancy to the 2 M BPT registers (M = 3 drops
-    // from three waves per SIMD to two; M = 2 with eight bins per thread
-    // beyond four sources, from two to one).
+    // and after each later source's update sigma^2 is formed again from L and
+    // H (M = 2) or changed by that source's own term (M = 4: two FMAs instead
+    // of N; formed again when the change cancels, see below). Phase A
+    // recomputes them from L and H every iteration, so rounding does not
+    // accumulate across iterations. The other shapes would lose occupancy to
+    // the 2 M BPT registers (M = 3 drops from three waves per SIMD to two;
+    // M = 2 with eight bins per thread beyond four sources, from two to one).
     constexpr bool kKeep = ((M == 2) && (BPT <= 4 || N <= 4)) || (M == 4 && BPT == 4);
+    // a running sigma^2 below this fraction of its previous value has lost
+    // more than two bits to cancellation and is formed again (a single
+    // precision emulation over twelve decades bounds the per-bin error by
+    // 8e-7 with it, 1e-4 with 1/64, and finds 3.6 without it)
+    constexpr float kSgDrop = 0.25f;
     float sg[kKeep ? BPT : 1][M];
     float wr[kKeep ? BPT : 1][M];
 #pragma unroll
@@ -674,6 +680,7 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
             }
             buf ^= 1;
             bad = bad || !good;
+            bool drop = false;  // some bin's sigma^2 fell below kSgDrop of its value
 #pragma unroll
             for (int k = 0; k < BPT; ++k) {
                 float s = 0.0f;
@@ -686,10 +693,42 @@ __device__ __forceinline__ void em_item(const WorkItem &it, int n_iter, int algo
                     if (n + 1 < N) {
 #pragma unroll
                         for (int m = 0; m < M; ++m) {
-                            sg[k][m] = fmaf(lam[n][m], vnew, fmaf(-lold[m], vold, sg[k][m]));
-                            wr[k][m] = rcp(sg[k][m]);
+                            if constexpr (M == 2) {
+                                // two channels: the sum itself costs one FMA more
+                                float t = 0.0f;
+#pragma unroll
+                                for (int nn = 0; nn < N; ++nn) t = fmaf(vr[k][nn], lam[nn][m], t);
+                                sg[k][m] = t;
+                            } else {
+                                const float sn = fmaf(lam[n][m], vnew, fmaf(-lold[m], vold, sg[k][m]));
+                                drop = drop || !(sn >= kSgDrop * sg[k][m]);
+                                sg[k][m] = sn;
+                            }
                         }
                     }
+                }
+            }
+            if constexpr (kKeep) {
+                if (n + 1 < N) {
+                    // Where the updated source dominated a bin and its term
+                    // collapsed, the subtraction above cancels most digits of
+                    // sigma^2; then (rarely) the whole wavefront forms the sums
+                    // again from L and H.
+                    if (M != 2 && __any(drop)) {
+#pragma unroll
+                        for (int k = 0; k < BPT; ++k)
+#pragma unroll
+                            for (int m = 0; m < M; ++m) {
+                                float t = 0.0f;
+#pragma unroll
+                                for (int nn = 0; nn < N; ++nn) t = fmaf(vr[k][nn], lam[nn][m], t);
+                                sg[k][m] = t;
+                            }
+                    }
+#pragma unroll
+                    for (int k = 0; k < BPT; ++k)
+#pragma unroll
+                        for (int m = 0; m < M; ++m) wr[k][m] = rcp(sg[k][m]);
                 }
             }
         }
