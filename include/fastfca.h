@@ -168,6 +168,9 @@ int fastfca_mnmf_set_params(fastfca_ctx *c, const fastfca_c128 *P, const float *
  * bin after each iteration (eq:negll, sign flipped, with the M ln(pi)
  * constant) is recorded for fastfca_ll_trace. Numerical failures freeze the
  * failing frequency and are reported by the next synchronizing call.
+ * Contexts of one (M, N, T) class are launched directly (one launch, plus
+ * those of the tail split); batches of several classes, the persistent
+ * schedule and FastMNMF replay a HIP graph captured once per n_iter.
  */
 int fastfca_em_step(fastfca_ctx *c, int n_iter);
 

@@ -920,6 +920,12 @@ int fastfca_em_step(fastfca_ctx *c, int n_iter) {
         if (rc != FASTFCA_OK) return rc;
     }
     c->last_n_iter = n_iter;
+    // One class (a single mixture, or a batch of equal shapes) is one launch,
+    // plus the tail split's few: launched directly, which leaves the stream
+    // free a few microseconds sooner than a graph does. Batches of several
+    // classes, the persistent queue and FastMNMF (three launches per
+    // iteration) replay a graph captured once per n_iter.
+    if (!c->mn && !c->persistent && c->classes.size() == 1) return record_em(c, n_iter);
     if (c->graph_exec && c->graph_n_iter == n_iter) {
         HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
         return FASTFCA_OK;
