@@ -168,6 +168,85 @@ __global__ void __launch_bounds__(kAuxThreads) loglik_kernel(const WorkItem *ite
 // precision Gauss-Jordan in LDS, a few microseconds that overlap across the
 // grid) instead of reading it from a separate inversion launch; a singular P
 // is recorded in the frequency's status by the workgroup of its first tile.
+// M = 2 without LDS or barriers: every thread forms P^{-1} = adj(P) / det P
+// in double precision from the frequency's P (the same pivot tests as the
+// elimination: the larger entry of column 0, then det P over it, against tol
+// times the largest entry), and reads lambda directly.
+__global__ void __launch_bounds__(kAuxThreads) mwf2_kernel(const WorkItem *items, int F, float2 *y) {
+    const int f = blockIdx.y;
+    const WorkItem &it = items[f];
+    const int T = it.Tx, N = it.N;
+    const cd p00 = ld(it.P[0]), p01 = ld(it.P[1]), p10 = ld(it.P[2]), p11 = ld(it.P[3]);
+    const double amax2 = fmax(fmax(abs2(p00), abs2(p01)), fmax(abs2(p10), abs2(p11)));
+    const double c0 = fmax(abs2(p00), abs2(p10));
+    const cd det = p00 * p11 - p01 * p10;
+    const double tol2 = kPivotTol * kPivotTol;
+    if (!(amax2 > 0.0) || !(amax2 < INFINITY) || !(c0 >= tol2 * amax2) || !(abs2(det) >= tol2 * amax2 * c0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *it.status = ST_SINGULAR;
+        return;
+    }
+    const cd id = rcp_d(abs2(det)) * conjd(det);
+    // B[r][c] = conj(P^{-1}[c][r]); P^{-1} = [[p11, -p01], [-p10, p00]] / det
+    const cd b00 = conjd(p11 * id), b01 = conjd(cmk(0.0, 0.0) - p10 * id);
+    const cd b10 = conjd(cmk(0.0, 0.0) - p01 * id), b11 = conjd(p00 * id);
+    const float2 Pf[4] = {make_float2(static_cast<float>(p00.re), static_cast<float>(p00.im)),
+                          make_float2(static_cast<float>(p01.re), static_cast<float>(p01.im)),
+                          make_float2(static_cast<float>(p10.re), static_cast<float>(p10.im)),
+                          make_float2(static_cast<float>(p11.re), static_cast<float>(p11.im))};
+    const float2 Bf[4] = {make_float2(static_cast<float>(b00.re), static_cast<float>(b00.im)),
+                          make_float2(static_cast<float>(b01.re), static_cast<float>(b01.im)),
+                          make_float2(static_cast<float>(b10.re), static_cast<float>(b10.im)),
+                          make_float2(static_cast<float>(b11.re), static_cast<float>(b11.im))};
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    constexpr int M = 2;
+    float2 x[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) x[r] = it.x[static_cast<size_t>(t) * M + r];
+    float2 z[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        float zr = 0.f, zi = 0.f;
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            const float2 p = Pf[r * M + m];
+            zr = fmaf(p.x, x[r].x, fmaf(p.y, x[r].y, zr));
+            zi = fmaf(p.x, x[r].y, fmaf(-p.y, x[r].x, zi));
+        }
+        z[m] = make_float2(zr, zi);
+    }
+    const float *vt = it.v + static_cast<size_t>(t / it.B) * N;
+    const float *lam = it.lam;
+    float rs[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        float s = 0.f;
+        for (int n = 0; n < N; ++n) s = fmaf(vt[n], lam[n * M + m], s);
+        rs[m] = rcp(s);
+    }
+    for (int n = 0; n < N; ++n) {
+        const float vn = vt[n];
+        float2 gz[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const float g = vn * lam[n * M + m] * rs[m];
+            gz[m] = make_float2(g * z[m].x, g * z[m].y);
+        }
+        float2 *yo = y + ((static_cast<size_t>(n) * F + f) * T + t) * M;
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            float ar = 0.f, ai = 0.f;
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const float2 b = Bf[r * M + c];
+                ar = fmaf(b.x, gz[c].x, fmaf(-b.y, gz[c].y, ar));
+                ai = fmaf(b.x, gz[c].y, fmaf(b.y, gz[c].x, ai));
+            }
+            yo[r] = make_float2(ar, ai);
+        }
+    }
+}
+
 template <int M>
 __global__ void __launch_bounds__(kAuxThreads) mwf_kernel(const WorkItem *items, int F, float2 *y) {
     __shared__ double2 A[M][2 * M];
@@ -403,6 +482,10 @@ hipError_t launch_loglik_terms(const WorkItem *items, int n_items, int M, const 
 
 hipError_t launch_mwf_bins(const WorkItem *items, int F, int T, int M, float2 *y, hipStream_t s) {
     dim3 grid((T + kAuxThreads - 1) / kAuxThreads, F);
+    if (M == 2) {
+        hipLaunchKernelGGL(mwf2_kernel, grid, dim3(kAuxThreads), 0, s, items, F, y);
+        return hipGetLastError();
+    }
 #define FFCA_CALL(MM) hipLaunchKernelGGL(mwf_kernel<MM>, grid, dim3(kAuxThreads), 0, s, items, F, y)
     FFCA_M_SWITCH(M, FFCA_CALL)
 #undef FFCA_CALL
