@@ -290,6 +290,7 @@ def main():
             "sample": "full workload: F=%d T=%d M=%d N=%d, %d IP+EM iterations + MWF, FP64 C, OpenMP over "
                       "frequencies, %.2f s" % (F, T, M, N, iters, t3 - t2),
             "cpu_model": cpu_model(),
+            "host_cpus": {"logical": os.cpu_count(), "usable": len(os.sched_getaffinity(0))},
             "one_core": {"value": F1 * T * N * iters / (t5 - t4), "unit": "updates/s", "cores": 1,
                          "sample": "F=%d of %d frequencies, %d IP+EM iterations, %.2f s" % (F1, F, iters, t5 - t4)},
         }
