@@ -513,6 +513,27 @@ typedef struct {
  */
 int fastfca_warmstart(fastfca_ctx *c, int b, const fastfca_net *net, int *n_taken);
 
+/*
+ * fastfca_warmstart_race -- the warm start judged by a race instead of by
+ * the starting likelihood. The current start of mixture b (A) and the new
+ * one (B: the network's, or with net == NULL the whitening-only start, as in
+ * fastfca_warmstart) both run race_iters >= 1 iterations of the context's
+ * algorithm (Algorithm 1, or 2 after fastfca_set_algorithm), side by side in
+ * one launch over 2F frequencies; then each frequency keeps the state with
+ * the higher log-likelihood per bin after the race (eq:negll, from the
+ * fused trace; a start whose run stopped with an error loses). The mixture's
+ * state is then race_iters iterations on from its better start, frequency by
+ * frequency; later fastfca_em_step calls continue from there. The starts
+ * often converge to different local optima of a frequency, so keeping the
+ * better one can raise the likelihood reached faster than either start.
+ *   n_taken  host int or NULL: the number of frequencies that kept B (the
+ *            call then synchronizes).
+ * Workspace as fastfca_warmstart, plus 16 F race_iters bytes of traces.
+ * Errors: as fastfca_warmstart; FASTFCA_E_ARG for race_iters < 1. The
+ * context's own trace (fastfca_ll_trace) is not written.
+ */
+int fastfca_warmstart_race(fastfca_ctx *c, int b, const fastfca_net *net, int race_iters, int *n_taken);
+
 /* ====================================================================
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.

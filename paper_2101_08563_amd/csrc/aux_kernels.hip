@@ -590,7 +590,8 @@ hipError_t launch_ws_whitened(const float2 *x, const double2 *P, float *lam, flo
 // the frequencies that kept the new start. One workgroup per frequency.
 __global__ void ws_select_kernel(const double *ll_old, const double *ll_new, double2 *P, float *lam, float *v,
                                  const double2 *P_old, const float *lam_old, const float *v_old, int T, int M,
-                                 int N, int *n_taken) {
+                                 int N, int *n_taken, int *status, const int *status_old, double *ldet,
+                                 const double *ldet_old) {
     const int f = blockIdx.x;
     const double a = ll_old[f], b = ll_new[f];
     const bool take = (b == b) && fabs(b) < INFINITY && b >= a;
@@ -603,13 +604,39 @@ __global__ void ws_select_kernel(const double *ll_old, const double *ll_new, dou
     for (int i = threadIdx.x; i < M * M; i += blockDim.x) P[fP + i] = P_old[fP + i];
     for (int i = threadIdx.x; i < N * M; i += blockDim.x) lam[fl + i] = lam_old[fl + i];
     for (int i = threadIdx.x; i < T * N; i += blockDim.x) v[fv + i] = v_old[fv + i];
+    if (threadIdx.x == 0) {
+        if (status) status[f] = status_old[f];
+        if (ldet) ldet[f] = ldet_old[f];
+    }
 }
 
 hipError_t launch_ws_select(const double *ll_old, const double *ll_new, double2 *P, float *lam, float *v,
                             const double2 *P_old, const float *lam_old, const float *v_old, int F, int T, int M,
-                            int N, int *n_taken, hipStream_t s) {
+                            int N, int *n_taken, hipStream_t s, int *status, const int *status_old, double *ldet,
+                            const double *ldet_old) {
     hipLaunchKernelGGL(ws_select_kernel, dim3(F), dim3(kAuxThreads), 0, s, ll_old, ll_new, P, lam, v, P_old,
-                       lam_old, v_old, T, M, N, n_taken);
+                       lam_old, v_old, T, M, N, n_taken, status, status_old, ldet, ldet_old);
+    return hipGetLastError();
+}
+
+// The race of two starts (fastfca_warmstart_race): per frequency the
+// likelihood after the last of the K iterations of either start, from the
+// traces the EM kernel wrote (start B in rows [0, F), start A in rows
+// [F, 2F), K entries each); -inf for a frequency whose run stopped with an
+// error, so that the other start is kept.
+__global__ void race_ll_kernel(const double *trace, int K, const int *st_b, const int *st_a, double *ll_b,
+                               double *ll_a, int F) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const double b = trace[static_cast<size_t>(f) * K + K - 1];
+    const double a = trace[static_cast<size_t>(F + f) * K + K - 1];
+    ll_b[f] = (st_b[f] == ST_OK && fabs(b) < INFINITY) ? b : -INFINITY;
+    ll_a[f] = (st_a[f] == ST_OK && fabs(a) < INFINITY) ? a : -INFINITY;
+}
+
+hipError_t launch_race_ll(const double *trace, int K, const int *st_b, const int *st_a, double *ll_b, double *ll_a,
+                          int F, hipStream_t s) {
+    hipLaunchKernelGGL(race_ll_kernel, dim3((F + 255) / 256), dim3(256), 0, s, trace, K, st_b, st_a, ll_b, ll_a, F);
     return hipGetLastError();
 }
 

@@ -30,7 +30,11 @@ hipError_t launch_ws_whitened(const float2 *x, const double2 *P, float *lam, flo
                               hipStream_t s);
 hipError_t launch_ws_select(const double *ll_old, const double *ll_new, double2 *P, float *lam, float *v,
                             const double2 *P_old, const float *lam_old, const float *v_old, int F, int T, int M,
-                            int N, int *n_taken, hipStream_t s);
+                            int N, int *n_taken, hipStream_t s, int *status = nullptr,
+                            const int *status_old = nullptr, double *ldet = nullptr,
+                            const double *ldet_old = nullptr);
+hipError_t launch_race_ll(const double *trace, int K, const int *st_b, const int *st_a, double *ll_b, double *ll_a,
+                          int F, hipStream_t s);
 hipError_t net_features(const float2 *x, int F, int T, int M, float eps, double2 *P0, float *feat, hipStream_t s);
 hipError_t net_forward_fused(const float *feat, int S, int M, int T, int C, int L, int N,
                              const uint16_t *const *Wb, const float *const *b, int Kp0, const float *Wv, int ldv,
@@ -95,6 +99,13 @@ struct WsScratch {
     WsBuf<double> ll_old;   // [F] per-frequency LL of the replaced start
     WsBuf<double> ll_new;   // [F] per-frequency LL of the new start
     WsBuf<int> taken;       // frequencies that kept the new start
+    // fastfca_warmstart_race: both starts' traces, the copy's ln|det P|^2 and
+    // status, and the work table of the 2F frequencies that race
+    WsBuf<double> race_trace;
+    WsBuf<double> race_ldet;
+    WsBuf<int> race_status;
+    WsBuf<WorkItem> race_items;
+    std::vector<WorkItem> race_host;  // the table as last uploaded
 };
 
 // FastMNMF state (fastfca_mnmf_init): NMF factors and the V-rule scratch.
@@ -1413,7 +1424,12 @@ void fastfca_destroy(fastfca_ctx *c) {
     delete c;
 }
 
-int fastfca_warmstart(fastfca_ctx *c, int b, const fastfca_net *net, int *n_taken) {
+}  // extern "C"
+
+namespace {
+
+// Argument checks shared by the two warm-start entry points.
+int ws_check(fastfca_ctx *c, int b, const fastfca_net *net) {
     if (!valid_problem(c, b)) return c ? set_err(c, FASTFCA_E_ARG, "bad mixture index %d", b) : FASTFCA_E_ARG;
     auto &p = c->probs[b];
     if (p.blocks || c->mn) return set_err(c, FASTFCA_E_STATE, "warm start: frame-model contexts only");
@@ -1430,25 +1446,22 @@ int fastfca_warmstart(fastfca_ctx *c, int b, const fastfca_net *net, int *n_take
         for (int l = 0; l <= net->L; ++l)
             if (!net->Wb[l] || !net->b[l]) return set_err(c, FASTFCA_E_ARG, "warm start: layer %d missing", l);
     }
+    return FASTFCA_OK;
+}
+
+// The new start of mixture b written over its state (features, and the
+// network's outputs or the whitening-only start), with the workspace it needs.
+int ws_new_start(fastfca_ctx *c, int b, const fastfca_net *net) {
+    auto &p = c->probs[b];
     const size_t F = p.F, T = p.T, M = p.M, N = p.N;
     auto &w = c->ws;
     int rc = FASTFCA_OK;
-    if ((rc = ws_reserve(c, w.feat, F * M * T)) != FASTFCA_OK || (rc = ws_reserve(c, w.P_old, F * M * M)) != FASTFCA_OK ||
-        (rc = ws_reserve(c, w.lam_old, F * N * M)) != FASTFCA_OK || (rc = ws_reserve(c, w.v_old, F * T * N)) != FASTFCA_OK ||
-        (rc = ws_reserve(c, w.ll_old, F)) != FASTFCA_OK || (rc = ws_reserve(c, w.ll_new, F)) != FASTFCA_OK ||
-        (rc = ws_reserve(c, w.taken, 1)) != FASTFCA_OK)
-        return rc;
+    if ((rc = ws_reserve(c, w.feat, F * M * T)) != FASTFCA_OK) return rc;
     if (net && ((rc = ws_reserve(c, w.lv, F * N * T)) != FASTFCA_OK ||
                 (rc = ws_reserve(c, w.part, F * ((T + 63) / 64) * net->C)) != FASTFCA_OK ||
                 (rc = ws_reserve(c, w.pooled, F * net->C)) != FASTFCA_OK || (rc = ws_reserve(c, w.ll, F * N * M)) != FASTFCA_OK))
         return rc;
     hipStream_t s = c->stream;
-    // the start being replaced and its likelihood per frequency
-    HIPCHK(c, hipMemcpyAsync(w.P_old.p, p.P, sizeof(double2) * F * M * M, hipMemcpyDeviceToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(w.lam_old.p, p.lam, sizeof(float) * F * N * M, hipMemcpyDeviceToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(w.v_old.p, p.v, sizeof(float) * F * T * N, hipMemcpyDeviceToDevice, s));
-    HIPCHK(c, launch_ldet(p.items, p.F, p.M, p.ldet, s));
-    HIPCHK(c, launch_loglik_terms(p.items, p.F, p.M, p.ldet, w.ll_old.p, s));
     // whitening P0 = C_f^{-1/2}, written as the new P, and the features
     HIPCHK(c, net_features(p.x, p.F, p.T, p.M, 1e-8f, p.P, w.feat.p, s));
     if (net) {
@@ -1459,6 +1472,31 @@ int fastfca_warmstart(fastfca_ctx *c, int b, const fastfca_net *net, int *n_take
     } else {
         HIPCHK(c, launch_ws_whitened(p.x, p.P, p.lam, p.v, p.F, p.T, p.M, p.N, s));
     }
+    return FASTFCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fastfca_warmstart(fastfca_ctx *c, int b, const fastfca_net *net, int *n_taken) {
+    int rc = ws_check(c, b, net);
+    if (rc != FASTFCA_OK) return rc;
+    auto &p = c->probs[b];
+    const size_t F = p.F, T = p.T, M = p.M, N = p.N;
+    auto &w = c->ws;
+    if ((rc = ws_reserve(c, w.P_old, F * M * M)) != FASTFCA_OK || (rc = ws_reserve(c, w.lam_old, F * N * M)) != FASTFCA_OK ||
+        (rc = ws_reserve(c, w.v_old, F * T * N)) != FASTFCA_OK || (rc = ws_reserve(c, w.ll_old, F)) != FASTFCA_OK ||
+        (rc = ws_reserve(c, w.ll_new, F)) != FASTFCA_OK || (rc = ws_reserve(c, w.taken, 1)) != FASTFCA_OK)
+        return rc;
+    hipStream_t s = c->stream;
+    // the start being replaced and its likelihood per frequency
+    HIPCHK(c, hipMemcpyAsync(w.P_old.p, p.P, sizeof(double2) * F * M * M, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(w.lam_old.p, p.lam, sizeof(float) * F * N * M, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(w.v_old.p, p.v, sizeof(float) * F * T * N, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, launch_ldet(p.items, p.F, p.M, p.ldet, s));
+    HIPCHK(c, launch_loglik_terms(p.items, p.F, p.M, p.ldet, w.ll_old.p, s));
+    if ((rc = ws_new_start(c, b, net)) != FASTFCA_OK) return rc;
     // judge: the new start's likelihood against the old one's, per frequency
     HIPCHK(c, launch_ldet(p.items, p.F, p.M, p.ldet, s));
     HIPCHK(c, launch_loglik_terms(p.items, p.F, p.M, p.ldet, w.ll_new.p, s));
@@ -1467,6 +1505,70 @@ int fastfca_warmstart(fastfca_ctx *c, int b, const fastfca_net *net, int *n_take
                                p.N, w.taken.p, s));
     // the likelihood kernels record a singular P of a rejected start
     HIPCHK(c, launch_fill_int(c->d_status + p.item0, p.F, ST_OK, s));
+    if (n_taken) {
+        int h = 0;
+        HIPCHK(c, hipMemcpyAsync(&h, w.taken.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        *n_taken = h;
+    }
+    return FASTFCA_OK;
+}
+
+int fastfca_warmstart_race(fastfca_ctx *c, int b, const fastfca_net *net, int race_iters, int *n_taken) {
+    int rc = ws_check(c, b, net);
+    if (rc != FASTFCA_OK) return rc;
+    if (race_iters < 1) return set_err(c, FASTFCA_E_ARG, "warm start race: race_iters = %d < 1", race_iters);
+    auto &p = c->probs[b];
+    const size_t F = p.F, T = p.T, M = p.M, N = p.N, K = race_iters;
+    auto &w = c->ws;
+    if ((rc = ws_reserve(c, w.P_old, F * M * M)) != FASTFCA_OK || (rc = ws_reserve(c, w.lam_old, F * N * M)) != FASTFCA_OK ||
+        (rc = ws_reserve(c, w.v_old, F * T * N)) != FASTFCA_OK || (rc = ws_reserve(c, w.ll_old, F)) != FASTFCA_OK ||
+        (rc = ws_reserve(c, w.ll_new, F)) != FASTFCA_OK || (rc = ws_reserve(c, w.taken, 1)) != FASTFCA_OK ||
+        (rc = ws_reserve(c, w.race_trace, 2 * F * K)) != FASTFCA_OK || (rc = ws_reserve(c, w.race_ldet, F)) != FASTFCA_OK ||
+        (rc = ws_reserve(c, w.race_status, F)) != FASTFCA_OK || (rc = ws_reserve(c, w.race_items, 2 * F)) != FASTFCA_OK)
+        return rc;
+    hipStream_t s = c->stream;
+    int *st_b = c->d_status + p.item0;
+    // start A, the current state, set aside; start B written over the state
+    HIPCHK(c, hipMemcpyAsync(w.P_old.p, p.P, sizeof(double2) * F * M * M, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(w.lam_old.p, p.lam, sizeof(float) * F * N * M, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(w.v_old.p, p.v, sizeof(float) * F * T * N, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, launch_fill_int(w.race_status.p, p.F, ST_OK, s));
+    HIPCHK(c, launch_fill_int(st_b, p.F, ST_OK, s));
+    if ((rc = ws_new_start(c, b, net)) != FASTFCA_OK) return rc;
+    // the work table of the race: B on the mixture's own state, A on the
+    // copy; each frequency's trace row holds K entries
+    std::vector<WorkItem> tab(2 * F);
+    for (size_t f = 0; f < F; ++f) {
+        WorkItem it = c->h_items[p.item0 + f];
+        it.status = st_b + f;
+        it.ll_trace = w.race_trace.p + f * K;
+        tab[f] = it;
+        it.P = w.P_old.p + f * M * M;
+        it.lam = w.lam_old.p + f * N * M;
+        it.v = w.v_old.p + f * T * N;
+        it.ldet = w.race_ldet.p + f;
+        it.status = w.race_status.p + f;
+        it.ll_trace = w.race_trace.p + (F + f) * K;
+        tab[F + f] = it;
+    }
+    const bool same = w.race_host.size() == tab.size() &&
+                      std::memcmp(w.race_host.data(), tab.data(), sizeof(WorkItem) * tab.size()) == 0;
+    if (!same) {
+        w.race_host = tab;
+        HIPCHK(c, hipMemcpyAsync(w.race_items.p, w.race_host.data(), sizeof(WorkItem) * tab.size(),
+                                 hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipStreamSynchronize(s));  // the host table may change on the next call
+    }
+    // both starts, race_iters iterations of the context's algorithm, in one launch
+    const auto &cc = c->classes[c->h_items[p.item0].cls];
+    EmLaunch a{w.race_items.p, static_cast<int>(2 * F), race_iters, nullptr, c->algo, c->ll_alarm, 0, 0};
+    HIPCHK(c, launch_class(cc, a, static_cast<int>(2 * F), s));
+    // keep per frequency the start with the higher likelihood after the race
+    HIPCHK(c, launch_race_ll(w.race_trace.p, race_iters, st_b, w.race_status.p, w.ll_new.p, w.ll_old.p, p.F, s));
+    HIPCHK(c, launch_fill_int(w.taken.p, 1, 0, s));
+    HIPCHK(c, launch_ws_select(w.ll_old.p, w.ll_new.p, p.P, p.lam, p.v, w.P_old.p, w.lam_old.p, w.v_old.p, p.F, p.T, p.M,
+                               p.N, w.taken.p, s, st_b, w.race_status.p, p.ldet, w.race_ldet.p));
     if (n_taken) {
         int h = 0;
         HIPCHK(c, hipMemcpyAsync(&h, w.taken.p, sizeof(int), hipMemcpyDeviceToHost, s));

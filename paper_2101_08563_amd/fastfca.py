@@ -69,6 +69,7 @@ SIGNATURES = {
     "fastfca_ws_targets": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _vp, _vp, _vp]),
     "fastfca_ws_apply": (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _vp, _vp]),
     "fastfca_warmstart": (_i, [_vp, _i, _vp, _pi]),
+    "fastfca_warmstart_race": (_i, [_vp, _i, _vp, _i, _pi]),
     "fastfca_fit_noalloc": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _vp, _vp]),
 }
 
@@ -340,6 +341,17 @@ class FastFCA:
         n = ctypes.c_int(0)
         self._chk(self._lib.fastfca_warmstart(self._ctx, b, ctypes.byref(desc) if desc is not None else None,
                                               ctypes.byref(n) if count else None))
+        return n.value if count else None
+
+    def warmstart_race(self, net=None, race_iters=100, b=0, count=False):
+        """fastfca_warmstart_race: run the current start and the new one (the
+        network's, or the whitening-only start with net=None) race_iters
+        iterations side by side and keep per frequency the better; count=True
+        synchronizes and returns how many frequencies kept the new start."""
+        desc = net.descriptor() if net is not None else None
+        n = ctypes.c_int(0)
+        self._chk(self._lib.fastfca_warmstart_race(self._ctx, b, ctypes.byref(desc) if desc is not None else None,
+                                                   int(race_iters), ctypes.byref(n) if count else None))
         return n.value if count else None
 
     def set_tail_split(self, blocks=-1):

@@ -120,7 +120,7 @@ def _timed(stream, fn, reps=3):
     return float(np.median(ts))
 
 
-def measure(weights, n_eval=64, conv_iters=1500, seed0=10**6, log=None):
+def measure(weights, n_eval=64, conv_iters=1500, seed0=10**6, log=None, race_iters=100, race_iters_white=150):
     """Measured time to converge on n_eval held-out mixtures (seeds seed0 + i,
     disjoint from the training seeds), one single-mixture context each.
 
@@ -135,7 +135,12 @@ def measure(weights, n_eval=64, conv_iters=1500, seed0=10**6, log=None):
     (the graph of each em_step length is captured before its timed runs).
     Also reported: the log-likelihood after the first iteration from either
     start, and how far the warm fit ends above or below LL* after
-    conv_iters iterations (a different local optimum shows there)."""
+    conv_iters iterations (a different local optimum shows there); and the
+    race judge (fastfca_warmstart_race): the seeded start and the network's
+    (race) or the whitening-only start (race_white) run race_iters
+    iterations side by side, each frequency keeps the better, and the plain
+    iteration continues; its iterations count the race's, its wall time is
+      race   fastfca_warmstart_race(net, K) + em_step(k_after)."""
     net = ConvNet.load(weights)
     stream = torch.cuda.current_stream()
     rows = []
@@ -172,6 +177,15 @@ def measure(weights, n_eval=64, conv_iters=1500, seed0=10**6, log=None):
         ctx.set_params(Pw, lam_p, v_p)
         ctx.em_step(conv_iters)
         kpf = _iters_to(ctx.ll_trace(), target)
+        # the race judge: both starts run race_iters iterations, each
+        # frequency keeps the better, then the plain iteration continues
+        race = {}
+        for arm, rnet, K in (("race", net, race_iters), ("race_white", None, race_iters_white)):
+            restart()
+            kept = ctx.warmstart_race(rnet, K, count=True)
+            ctx.em_step(conv_iters)
+            ka = _iters_to(ctx.ll_trace(), target)
+            race[arm] = (K + ka if ka is not None else None, kept, ka)
         # timed runs
         ctx.em_step(kp)
         ts = []
@@ -189,8 +203,24 @@ def measure(weights, n_eval=64, conv_iters=1500, seed0=10**6, log=None):
                 restart()
                 tw.append(_timed(stream, lambda: (ctx.warmstart(net), ctx.em_step(kw)), reps=1))
             t_warm, t_ws = float(np.median(tw)), float(np.median(tws))
+        for arm, rnet, K in (("race", net, race_iters), ("race_white", None, race_iters_white)):
+            kr, kept, ka = race[arm]
+            t_r = None
+            if ka is not None:
+                restart()
+                ctx.warmstart_race(rnet, K)
+                ctx.em_step(ka)
+                tr_ = []
+                for _ in range(3):
+                    restart()
+                    tr_.append(_timed(stream, lambda: (ctx.warmstart_race(rnet, K), ctx.em_step(ka)), reps=1))
+                t_r = float(np.median(tr_))
+            race[arm] = (kr, kept, t_r)
         ctx.close()
-        rows.append(dict(id=seed0 + i, ll_star=llstar, ll_first_plain=float(tr_p[0]), ll_first_warm=float(tr_w[0]),
+        rows.append(dict(id=seed0 + i, k_race=race["race"][0], kept_race=race["race"][1], ms_race=race["race"][2],
+                         k_race_white=race["race_white"][0], kept_race_white=race["race_white"][1],
+                         ms_race_white=race["race_white"][2],
+                         ll_star=llstar, ll_first_plain=float(tr_p[0]), ll_first_warm=float(tr_w[0]),
                          ll_end_warm_minus_star=float(tr_w[-1]) - llstar,
                          k_plain=kp, k_warm=kw, k_heur=kh, k_perfect=kpf,
                          taken=taken, ms_plain=t_plain, ms_warm=t_warm, ms_warmstart=t_ws))
@@ -214,6 +244,13 @@ def measure(weights, n_eval=64, conv_iters=1500, seed0=10**6, log=None):
                "frequencies_kept_median": med("taken"),
                "ll_first_iter_plain_median": med("ll_first_plain"), "ll_first_iter_warm_median": med("ll_first_warm"),
                "ll_end_warm_minus_star_median": med("ll_end_warm_minus_star")}
+    wr = np.array([r["ms_race"] if r["ms_race"] is not None else np.inf for r in rows], float)
+    wrw = np.array([r["ms_race_white"] if r["ms_race_white"] is not None else np.inf for r in rows], float)
+    summary.update({"race_iters": race_iters, "race_iters_white": race_iters_white,
+                    "race_ms_median": float(np.median(wr)), "race_total_iters_median": med("k_race"),
+                    "race_kept_median": med("kept_race"), "race_faster_frac": float(np.mean(wr < wp)),
+                    "race_white_ms_median": float(np.median(wrw)), "race_white_total_iters_median": med("k_race_white"),
+                    "race_white_kept_median": med("kept_race_white"), "race_white_faster_frac": float(np.mean(wrw < wp))})
     return summary, rows
 
 

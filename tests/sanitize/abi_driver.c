@@ -53,6 +53,7 @@ int main(void)
     expect("set_ll_alarm NULL", fastfca_set_ll_alarm(NULL, 1e-3), FASTFCA_E_ARG);
     expect("set_tail_split NULL", fastfca_set_tail_split(NULL, 4), FASTFCA_E_ARG);
     expect("warmstart NULL", fastfca_warmstart(NULL, 0, NULL, NULL), FASTFCA_E_ARG);
+    expect("warmstart_race NULL", fastfca_warmstart_race(NULL, 0, NULL, 10, NULL), FASTFCA_E_ARG);
     fastfca_destroy(NULL);
     /* the allocation-free entry point: argument and size checks */
     void *p = (void *)(uintptr_t)4096;

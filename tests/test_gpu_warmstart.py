@@ -135,3 +135,62 @@ def test_warm_start_rejects_a_mismatched_network():
         ctx.warmstart(ConvNet(M=2, N=4, C=16, L=1))
     assert e.value.code == -1
     ctx.close()
+
+
+# ------------------------------------------------------------------ fastfca_warmstart_race
+def test_race_with_a_failing_start_equals_the_plain_run_bitwise():
+    """A network whose start fails (NaN powers) loses the race in every
+    frequency: the state after the race is the plain run's after the same
+    number of iterations, bit for bit, and the context goes on from there."""
+    M, N, K = 2, 3, 15
+    x = _mixture(M=M, N=N)
+    plain = FastFCA(x, N, seed=11)
+    plain.em_step(K)
+    race = FastFCA(x, N, seed=11)
+    kept = race.warmstart_race(_bad_net(M, N, "nan"), K, count=True)
+    assert kept == 0
+    for a, b in zip(_params(plain), _params(race)):
+        assert np.array_equal(a, b)
+    # the context goes on from there like the plain run
+    plain.em_step(5)
+    race.em_step(5)
+    plain.sync()
+    race.sync()
+    for a, b in zip(_params(plain), _params(race)):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("which", ["whitening", "network"])
+def test_race_keeps_the_better_start_per_frequency(which):
+    """The seeded start against the whitening-only start or the trained
+    network's, 100 iterations each, on a headline-shaped mixture: no
+    frequency ends below the plain run after the same iterations (up to the
+    single precision trace the choice is made on), the frequencies that kept
+    the new start end above it, and the state is finite."""
+    from paper_2101_08563_amd.fastfca import synth_mixture
+    M, N, K = 2, 3, 100
+    x = synth_mixture(513, 1000, M, N, seed=4242)
+    net = ConvNet.load(WEIGHTS) if which == "network" else None
+    plain = FastFCA(x, N, seed=5)
+    plain.em_step(K)
+    _, llf_plain = plain.loglik(per_f=True)
+    race = FastFCA(x, N, seed=5)
+    kept = race.warmstart_race(net, K, count=True)
+    race.sync()
+    _, llf_race = race.loglik(per_f=True)
+    a, b = llf_plain.cpu().numpy(), llf_race.cpu().numpy()
+    print("race (%s) kept the new start in %d of 513 frequencies; LL per bin plain %.6f race %.6f"
+          % (which, kept, a.mean(), b.mean()), flush=True)
+    assert 0 <= kept <= 513
+    assert np.all(b >= a - 1e-5)
+    assert b.mean() >= a.mean()
+    assert all(np.isfinite(t).all() for t in _params(race))
+
+
+def test_race_rejects_bad_arguments():
+    x = _mixture(F=8, T=64)
+    ctx = FastFCA(x, 3, seed=1)
+    from paper_2101_08563_amd.fastfca import FastFCAError
+    with pytest.raises(FastFCAError):
+        ctx.warmstart_race(None, 0)
+    ctx.close()
