@@ -315,13 +315,16 @@ def main():
 
 def time_to_converge(n_eval=64, conv_iters=1500):
     """Second half of the metric, measured end to end: wall time for plain
-    IP+EM and for the warm start (fastfca_warmstart: features, network,
-    judge; then IP+EM) to reach the plain fit's log-likelihood after
-    conv_iters iterations minus 1e-2 nats/bin, medians over n_eval held-out
-    headline-shaped mixtures (paper_2101_08563_amd.train_warmstart.measure)."""
+    IP+EM and for the warm starts to reach the plain fit's log-likelihood
+    after conv_iters iterations minus 1e-2 nats/bin, medians over n_eval
+    held-out headline-shaped mixtures (paper_2101_08563_amd.train_warmstart.
+    measure): fastfca_warmstart (features, network, judge by the starting
+    likelihood) then IP+EM; and fastfca_warmstart_race (the network's start,
+    or the whitening-only one, raced against the seeded start, each
+    frequency keeping the better) then IP+EM."""
     import contextlib
 
-    weights = os.path.join(ROOT, "paper_2101_08563_amd", "data", "warmstart_c64l8.npz")
+    weights = os.path.join(ROOT, "paper_2101_08563_amd", "data", "warmstart_c32l4.npz")
     try:
         from paper_2101_08563_amd import train_warmstart
         with contextlib.redirect_stdout(sys.stderr):

@@ -99,7 +99,8 @@ def _iters_to(trace, target):
 
 
 def cmd_eval(args):
-    summary, rows = measure(args.weights, args.n_eval, args.conv_iters, log=log)
+    summary, rows = measure(args.weights, args.n_eval, args.conv_iters, log=log, race_iters=args.race_iters,
+                            race_iters_white=args.race_iters_white)
     log(json.dumps(summary))
     if args.out:
         with open(args.out, "w") as fh:
@@ -285,6 +286,8 @@ def main(argv=None):
     e.add_argument("--n-eval", type=int, default=512)
     e.add_argument("--conv-iters", type=int, default=1500)
     e.add_argument("--out", default="")
+    e.add_argument("--race-iters", type=int, default=100)
+    e.add_argument("--race-iters-white", type=int, default=150)
     args = ap.parse_args(argv)
     {"train": cmd_train, "train-stream": cmd_train_stream, "eval": cmd_eval}[args.cmd](args)
 

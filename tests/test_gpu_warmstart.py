@@ -18,7 +18,7 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2101_08563_amd", "data",
-                       "warmstart_c64l8.npz")
+                       "warmstart_c32l4.npz")
 
 
 def test_warm_start_gain_is_measured():
