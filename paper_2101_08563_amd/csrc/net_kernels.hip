@@ -193,7 +193,9 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(const float *X, int Cin, 
 // the same k order and the same MFMA sequence as conv_fwd_kernel; the
 // residual stream stays FP32 (hf), and the BF16 copy that feeds the MFMAs
 // alternates between two buffers, so a wave stores each 16-frame block of a
-// layer as soon as it is done, with one barrier per layer. The head (N outputs) and the per-tile sums of h_L over frames are
+// layer as soon as it is done, with one barrier per layer. The LDS buffers
+// are sized for the instance's C, so narrower networks keep more workgroups
+// per CU. The head (N outputs) and the per-tile sums of h_L over frames are
 // plain FP32; the tile sums are combined in order by pool_tiles_kernel.
 constexpr int kFT = 64;                                // output frames per tile
 constexpr int kFMaxL = 8;                              // residual layers
@@ -213,11 +215,11 @@ struct FusedNetArgs {
 
 template <int C>
 __global__ void __launch_bounds__(256) net_fused_fwd_kernel(FusedNetArgs a) {
-    __shared__ __align__(16) float hf[kFRows][kMaxC + 1];
-    __shared__ __align__(16) uint16_t hb[2][kFRows][kMaxC + 4];  // layer input / output, alternating
+    __shared__ __align__(16) float hf[kFRows][C + 1];
+    __shared__ __align__(16) uint16_t hb[2][kFRows][C + 4];  // layer input / output, alternating
     __shared__ __align__(16) uint16_t fb[kFRows][4];
-    __shared__ float wvs[kFMaxN][kMaxC];
-    __shared__ float bs[kFMaxL + 1][kMaxC];
+    __shared__ float wvs[kFMaxN][C];
+    __shared__ float bs[kFMaxL + 1][C];
     const int s = blockIdx.y, tile = blockIdx.x;
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
@@ -227,8 +229,8 @@ __global__ void __launch_bounds__(256) net_fused_fwd_kernel(FusedNetArgs a) {
     const int W0 = kFT + 2 * H;
     const int t0 = tile * kFT;
     const int fr0 = t0 - H;  // frame of row 0
-    static_assert((2 * kFRows * (kMaxC + 4) * 2) % 16 == 0, "16-byte clears");
-    for (int i = tid; i < 2 * kFRows * (kMaxC + 4) * 2 / 16; i += 256)
+    static_assert((2 * kFRows * (C + 4) * 2) % 16 == 0, "16-byte clears");
+    for (int i = tid; i < 2 * kFRows * (C + 4) * 2 / 16; i += 256)
         reinterpret_cast<uint4 *>(&hb[0][0][0])[i] = make_uint4(0u, 0u, 0u, 0u);
     for (int i = tid; i < kFRows * 2; i += 256) reinterpret_cast<uint32_t *>(&fb[0][0])[i] = 0u;
     for (int i = tid; i < a.N * C; i += 256) wvs[i / C][i % C] = a.Wv[static_cast<size_t>(i / C) * a.ldv + i % C];
@@ -245,7 +247,7 @@ __global__ void __launch_bounds__(256) net_fused_fwd_kernel(FusedNetArgs a) {
     // output rows [lo, hi) of a layer: activation, residual, zero padding
     // (res: the residual values of the lane's four outputs, zero for layer 0)
     auto store = [&](int l, int j, int lo, int hi, const f32x4 &c, const f32x4 &res,
-                     uint16_t (*out)[kMaxC + 4]) {
+                     uint16_t (*out)[C + 4]) {
         const int r = lo + 16 * j + li;
         if (r >= hi) return;
         const int t = fr0 + r;
@@ -311,8 +313,8 @@ __global__ void __launch_bounds__(256) net_fused_fwd_kernel(FusedNetArgs a) {
 
     // residual layers: input hb[(l + 1) & 1], output hb[l & 1]
     for (int l = 1; l <= L; ++l) {
-        uint16_t (*in)[kMaxC + 4] = hb[(l + 1) & 1];
-        uint16_t (*out)[kMaxC + 4] = hb[l & 1];
+        uint16_t (*in)[C + 4] = hb[(l + 1) & 1];
+        uint16_t (*out)[C + 4] = hb[l & 1];
         const int lo = 2 * (l + 1), hi = W0 - 2 * (l + 1);
         const int nblk = (hi - lo + 15) / 16;
         if (act) {
