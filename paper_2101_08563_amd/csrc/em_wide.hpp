@@ -74,11 +74,24 @@ constexpr int wide_region_floats() {
     return a > c ? a : c;
 }
 
-// x_t of bin t (zero for a bin past the end).
+// x_t of bin t (zero for a bin past the end). The frames sit in global
+// memory: loads through the global address space compile to global_load,
+// where a plain pointer read from the work item gives flat_load, whose
+// completion the next LDS wait would also wait for. A bin past the end reads
+// bin 0 (T >= 1) and discards it. Callers add an opaque zero to t inside
+// their loop over the bins: hoisted out of the iteration loop, the addresses
+// of all the bins would be kept (and spilled) across it.
+typedef float wf2 __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) wf2 *gx_ptr;
 template <int M>
-__device__ __forceinline__ void load_bins(const float2 *x, int t, bool valid, float2 (&out)[M]) {
+__device__ __forceinline__ void load_bins(gx_ptr x, int t, int T, float2 (&out)[M]) {
+    const bool valid = t < T;
+    const unsigned idx = valid ? static_cast<unsigned>(t) * M : 0u;
 #pragma unroll
-    for (int r = 0; r < M; ++r) out[r] = valid ? x[t * M + r] : make_float2(0.f, 0.f);
+    for (int r = 0; r < M; ++r) {
+        const wf2 v = x[idx + r];
+        out[r] = valid ? make_float2(v.x, v.y) : make_float2(0.f, 0.f);
+    }
 }
 
 template <int M, int N, int BPT>
@@ -94,6 +107,7 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, dou
     const int T = it.T;
     const float invTf = 1.0f / static_cast<float>(T);
     const double invT = 1.0 / static_cast<double>(T);
+    const gx_ptr xg = (gx_ptr)it.x;  // read once: later global stores could alias the work item
 
     float vr[BPT][N];
     float U[BPT][M];
@@ -145,8 +159,8 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, dou
     int status = ST_OK;
     for (int iter = 0; iter <= n_iter; ++iter) {
         const bool last = (iter == n_iter);
-        // ---------------- phase A: sigma^2, Q_m. The x of the next group of
-        // bins is requested before the current group is processed.
+        // ---------------- phase A: sigma^2, Q_m. The x of a group of bins is
+        // requested before the group's weights 1/sigma^2 are formed.
         if (!last && active) {
 #pragma unroll
             for (int m = 0; m < M; ++m) qd[(grp * M + m) * M2 + e] = 0.0;
@@ -157,7 +171,7 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, dou
             int loff = 0;
             asm volatile("" : "+v"(loff));
             float2 xk[M];
-            if (!last) load_bins<M>(it.x, tid + k * nthr, valid, xk);
+            if (!last) load_bins<M>(xg, tid + k * nthr + loff, T, xk);
             if (!last) {
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
@@ -249,12 +263,16 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, dou
             for (int r = 0; r < M; ++r) pcol[r] = sm.P32[r * M + mb];
             float *us = stg + 64 * M * 2;  // [64][M]
             float2 xn[M];
-            load_bins<M>(it.x, tid, vmask & 1u, xn);
+            load_bins<M>(xg, tid, T, xn);
 #pragma unroll
             for (int k = 0; k < BPT; ++k) {
 #pragma unroll
                 for (int r = 0; r < M; ++r) xs[lane * M + r] = xn[r];
-                if (k + 1 < BPT) load_bins<M>(it.x, tid + (k + 1) * nthr, (vmask >> (k + 1)) & 1u, xn);
+                if (k + 1 < BPT) {
+                    int z = 0;
+                    asm volatile("" : "+v"(z));
+                    load_bins<M>(xg, tid + (k + 1) * nthr + z, T, xn);
+                }
                 if (slot < S) {
 #pragma unroll 2
                     for (int b = slot; b < 64; b += S) {

@@ -634,18 +634,20 @@ __global__ void adamw_kernel(float *p, const float *g, float *m, float *v, size_
 //   C = (1/T) sum_t x_t x_t^H, P0 = C^{-1/2} (Hermitian inverse square root by
 //   the coupled Newton-Schulz iteration in double precision), feat[m][t] =
 //   ln(|(P0^H x_t)_m|^2 + eps) - mean_t(...). Writes P0 [M][M] (complex128) and
-//   feat [M][T] (float). M <= 4.
+//   feat [M][T] (float). M <= 4, a template argument so that the small
+//   matrices stay in registers.
 constexpr int kFeatMaxM = 4;
-__global__ void __launch_bounds__(256) features_kernel(const float2 *x, int T, int M, float eps,
-                                                       double2 *P0, float *feat) {
+template <int M>
+__global__ void __launch_bounds__(256) features_kernel(const float2 *x, int T, float eps, double2 *P0,
+                                                       float *feat) {
     const int f = blockIdx.x;
     const int tid = threadIdx.x;
     const float2 *xf = x + static_cast<size_t>(f) * T * M;
-    __shared__ double red[4][kFeatMaxM * kFeatMaxM * 2];
-    __shared__ double2 Ps[kFeatMaxM * kFeatMaxM];
-    __shared__ float mred[4][kFeatMaxM];
+    __shared__ double red[4][M * M * 2];
+    __shared__ double2 Ps[M * M];
+    __shared__ float mred[4][M];
     // covariance (double accumulation)
-    double acc[kFeatMaxM * kFeatMaxM * 2];
+    double acc[M * M * 2];
     for (int i = 0; i < M * M * 2; ++i) acc[i] = 0.0;
     for (int t = tid; t < T; t += blockDim.x) {
         for (int r = 0; r < M; ++r) {
@@ -663,7 +665,7 @@ __global__ void __launch_bounds__(256) features_kernel(const float2 *x, int T, i
     }
     __syncthreads();
     if (tid == 0) {
-        double Cr[kFeatMaxM][kFeatMaxM], Ci[kFeatMaxM][kFeatMaxM];
+        double Cr[M][M], Ci[M][M];
         for (int r = 0; r < M; ++r)
             for (int c = 0; c < M; ++c) {
                 const int i = (r * M + c) * 2;
@@ -677,8 +679,8 @@ __global__ void __launch_bounds__(256) features_kernel(const float2 *x, int T, i
         for (int r = 0; r < M; ++r)
             for (int c = 0; c < M; ++c) fn += Cr[r][c] * Cr[r][c] + Ci[r][c] * Ci[r][c];
         fn = sqrt(fn);
-        double Yr[kFeatMaxM][kFeatMaxM], Yi[kFeatMaxM][kFeatMaxM];
-        double Zr[kFeatMaxM][kFeatMaxM], Zi[kFeatMaxM][kFeatMaxM];
+        double Yr[M][M], Yi[M][M];
+        double Zr[M][M], Zi[M][M];
         for (int r = 0; r < M; ++r)
             for (int c = 0; c < M; ++c) {
                 Yr[r][c] = Cr[r][c] / fn;
@@ -687,7 +689,7 @@ __global__ void __launch_bounds__(256) features_kernel(const float2 *x, int T, i
                 Zi[r][c] = 0.0;
             }
         for (int it = 0; it < 100; ++it) {
-            double Sr[kFeatMaxM][kFeatMaxM], Si[kFeatMaxM][kFeatMaxM];
+            double Sr[M][M], Si[M][M];
             double dev = 0.0;
             for (int r = 0; r < M; ++r)
                 for (int c = 0; c < M; ++c) {
@@ -702,8 +704,8 @@ __global__ void __launch_bounds__(256) features_kernel(const float2 *x, int T, i
                     Si[r][c] = -0.5 * zi;
                 }
             if (dev < 1e-28) break;
-            double Yn_r[kFeatMaxM][kFeatMaxM], Yn_i[kFeatMaxM][kFeatMaxM];
-            double Zn_r[kFeatMaxM][kFeatMaxM], Zn_i[kFeatMaxM][kFeatMaxM];
+            double Yn_r[M][M], Yn_i[M][M];
+            double Zn_r[M][M], Zn_i[M][M];
             for (int r = 0; r < M; ++r)
                 for (int c = 0; c < M; ++c) {
                     double yr = 0.0, yi = 0.0, zr = 0.0, zi = 0.0;
@@ -738,7 +740,7 @@ __global__ void __launch_bounds__(256) features_kernel(const float2 *x, int T, i
     }
     __syncthreads();
     // features and their mean over t
-    float msum[kFeatMaxM];
+    float msum[M];
     for (int m = 0; m < M; ++m) msum[m] = 0.0f;
     float *ff = feat + static_cast<size_t>(f) * M * T;
     for (int t = tid; t < T; t += blockDim.x) {
@@ -978,8 +980,13 @@ hipError_t net_adamw(float *p, const float *g, float *m, float *v, size_t n, flo
 
 hipError_t net_features(const float2 *x, int F, int T, int M, float eps, double2 *P0, float *feat,
                         hipStream_t s) {
-    if (M < 1 || M > kFeatMaxM) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(features_kernel, dim3(F), dim3(256), 0, s, x, T, M, eps, P0, feat);
+    switch (M) {
+        case 1: hipLaunchKernelGGL(features_kernel<1>, dim3(F), dim3(256), 0, s, x, T, eps, P0, feat); break;
+        case 2: hipLaunchKernelGGL(features_kernel<2>, dim3(F), dim3(256), 0, s, x, T, eps, P0, feat); break;
+        case 3: hipLaunchKernelGGL(features_kernel<3>, dim3(F), dim3(256), 0, s, x, T, eps, P0, feat); break;
+        case 4: hipLaunchKernelGGL(features_kernel<4>, dim3(F), dim3(256), 0, s, x, T, eps, P0, feat); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
