@@ -67,6 +67,8 @@ __device__ __noinline__ int ip_inv(const double *qtot, double2 *Pd, float2 *P32,
     constexpr int NS = (NE + 63) / 64;  // entries per lane
     const int lane = threadIdx.x & 63;
     constexpr int NR = M * M + W2;      // entries of the M + 1 pivot rows
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) d2 lds_d2;
     double2 *buf0 = reinterpret_cast<double2 *>(scratch);
     double2 *buf1 = buf0 + NE;
     double2 *prow_n = buf1 + NE;        // pivot rows over their pivots: Q_t's at t M, P's at M^2
@@ -120,6 +122,10 @@ __device__ __noinline__ int ip_inv(const double *qtot, double2 *Pd, float2 *P32,
     bool sing = false;
     const double2 *src = buf0;
     double2 *dst = buf1;
+    // LDS views of the buffers (32-bit addresses, no generic-pointer checks)
+    const lds_d2 *Rn = (const lds_d2 *)prow_n;  // the pivot rows, then the reciprocals at NR
+    const lds_d2 *src_l = (const lds_d2 *)buf0;
+    lds_d2 *dst_l = (lds_d2 *)buf1;
 #pragma unroll 1
     for (int k = 0; k < M && !sing; ++k) {
         const double2 *X = src + NQ;
@@ -152,36 +158,56 @@ __device__ __noinline__ int ip_inv(const double *qtot, double2 *Pd, float2 *P32,
             if (j == 0) ipiv_n[t] = st(ip);
             if (fq && j == 0) qbad = !(piv.re >= kPivotTol * esc[t]);
         }
-        // every entry: one multiply-add with the normalized pivot row
+        // every entry: one multiply-add with the normalized pivot row,
+        //   new = (row k) ? r : base - c r,
+        // with c the entry's column-k element, r the normalized pivot row's
+        // element (for column k of a Q_m, which takes column k of the
+        // inverse in place: the pivot reciprocal) and base the entry itself
+        // (zero for column k of a Q_m). The entries go in batches of four whose
+        // LDS reads are all issued before any is used; no lane branches.
+        {
+            const lds_d2 *S = src_l;
+            lds_d2 *D = dst_l;
+            constexpr int B = 4;
 #pragma unroll
-        for (int q = 0; q < NS; ++q) {
-            const int e = lane + 64 * q;
-            if (e >= NE) continue;
-            cd nv;
-            if (e < NQ) {
-                const int t = e / M2, i = (e / M) % M, j = e % M;
-                const double2 *Qt = src + t * M2;
-                const cd acol = ld(Qt[i * M + k]);
-                if (j == k) {
-                    // in place: column k of the inverse replaces column k
-                    const cd ip = ld(ipiv_n[t]);
-                    nv = i == k ? ip : cmk(0.0, 0.0) - acol * ip;
-                } else {
-                    const cd pr = ld(prow_n[t * M + j]);
-                    nv = i == k ? pr : ld(Qt[i * M + j]) - acol * pr;
+            for (int q0 = 0; q0 < NS; q0 += B) {
+                d2 av[B], cv[B], rv[B];
+                bool rowk[B], zero[B], live[B];
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    if (q0 + u >= NS) break;
+                    const int e0 = lane + 64 * (q0 + u);
+                    live[u] = e0 < NE;
+                    const int e = live[u] ? e0 : 0;
+                    const bool isq = e < NQ;
+                    const int fq = isq ? e : e - NQ;
+                    const int t = fq / M2, i = isq ? (fq / M) % M : fq / W2, j = isq ? fq % M : fq % W2;
+                    const int s_ = i == k ? p : (i == p ? k : i);  // P's rows, swapped
+                    const int rowbase = isq ? t * M2 + i * M : NQ + s_ * W2;
+                    rowk[u] = i == k;
+                    zero[u] = isq && j == k;
+                    const int ri = isq ? (j == k ? NR + t : t * M + j) : M * M + j;
+                    av[u] = S[rowbase + j];
+                    cv[u] = S[rowbase + k];
+                    rv[u] = Rn[ri];
                 }
-            } else {
-                const int i = (e - NQ) / W2, j = (e - NQ) % W2;
-                const int s = i == k ? p : (i == p ? k : i);
-                const cd pr = ld(prow_n[M * M + j]);
-                nv = i == k ? pr : ld(X[s * W2 + j]) - ld(X[s * W2 + k]) * pr;
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    if (q0 + u >= NS) break;
+                    const cd r = cmk(rv[u].x, rv[u].y);
+                    const cd base = zero[u] ? cmk(0.0, 0.0) : cmk(av[u].x, av[u].y);
+                    const cd nv = rowk[u] ? r : base - cmk(cv[u].x, cv[u].y) * r;
+                    if (live[u]) D[lane + 64 * (q0 + u)] = d2{nv.re, nv.im};
+                }
             }
-            dst[e] = st(nv);
         }
         sing = __any(qbad) || !(best >= kPivotTol * kPivotTol * pscale);
         const double2 *t = src;
         src = dst;
         dst = const_cast<double2 *>(t);
+        const lds_d2 *tl = src_l;
+        src_l = dst_l;
+        dst_l = const_cast<lds_d2 *>(tl);
     }
     if (sing) return ST_SINGULAR;
 
