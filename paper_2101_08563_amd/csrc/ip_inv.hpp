@@ -48,7 +48,7 @@ constexpr int ip_inv_scratch_doubles() {
 // row swap) and the pivot reciprocals, one or two entries per lane, so that
 // the update of an entry is one complex multiply-add; and instead of keeping
 // the new values in registers until all reads of the step are done, it reads
-// one LDS copy of the matrices and writes the other (`scratch`,
+// one LDS copy of the matrices and writes the other (`scratch`, in LDS,
 // caller-provided and 16-byte aligned, ip_inv_scratch_doubles<M>() doubles;
 // the wavefront's LDS instructions execute in order, so no barrier is
 // needed). The sums of
