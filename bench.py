@@ -14,7 +14,8 @@ Prints ONE JSON line. Besides the contract fields it carries:
                    (flops_per_bin) over its event-timed duration against the
                    published 157.3 TFLOP/s FP32 peak; beside it the kernel's
                    own operation count against the one-FMA-per-lane rate and
-                   the HBM streaming-equivalent fractions
+                   the HBM streaming-equivalent fractions, and the bandwidth
+                   of a plain 1 GiB device copy on the same box
   cpu_baseline     the FP64 oracle on all host cores and on one core
   time_to_converge plain vs warm start, measured end to end (HIP events)
   extra            the batch32, 256-mixture batch and large-array lines
@@ -146,6 +147,29 @@ def calib_copy(mib):
     return 2 * n * 4
 
 
+def copy_bandwidth(mib=1024, reps=10):
+    """HBM bandwidth of a plain device-to-device copy of mib MiB on this machine,
+    timed with HIP events on the current stream: bytes read plus bytes
+    written per second, in GB/s. A reference for the kernels' roofline
+    fractions (what a pure streaming kernel reaches here against the 8 TB/s
+    peak)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(s)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,6 +290,7 @@ def main():
     }
     out["roofline"]["em_ms_per_call"] = em_ms
     out["roofline"]["hbm_algorithmic_bytes_per_launch"] = em_bytes_per_bin(M, N) * F * T
+    out["roofline"]["copy_kernel_GBps"] = copy_bandwidth()
     if args.calib_copy:
         out["calib_copy_bytes"] = calib_copy(args.calib_copy)
 
