@@ -140,6 +140,17 @@ def test_features_and_targets_match_reference():
     np.testing.assert_allclose(np.log(v.cpu().numpy()).transpose(0, 2, 1), tv.cpu().numpy(), rtol=1e-5, atol=1e-5)
 
 
+@pytest.mark.parametrize("M,T", [(3, 257), (4, 1000)])
+def test_features_match_reference_over_channels(M, T):
+    # the features kernel is compiled once per channel count (M = 1..4)
+    from paper_2101_08563_amd import synth
+    x = synth.mixture(F=5, T=T, M=M, N=M + 1, rank=4, config_id=81)
+    P0, feat = warmstart.features(t(x, torch.complex64), eps=1e-8)
+    rP0, rfeat = net_ref.features(x, 1e-8)
+    np.testing.assert_allclose(P0.cpu().numpy(), rP0, rtol=1e-6, atol=1e-9)
+    assert np.abs(feat.cpu().numpy() - rfeat).max() < 1e-3
+
+
 def test_training_reduces_the_loss():
     rng = np.random.default_rng(7)
     S, M, N, T = 64, 2, 3, 128
