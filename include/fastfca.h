@@ -266,8 +266,9 @@ enum {
 /*
  * fastfca_set_algorithm -- choose the L/H update of later fastfca_em_step
  * calls (Sec. IV-E: Algorithm 1 or Algorithm 2; the IP update of P and the
- * log-likelihood are shared). IP+MM is compiled for the shapes that run on
- * chip (M <= 4, N <= 8, T <= 2048): E_UNSUPPORTED otherwise.
+ * log-likelihood are shared), for every shape fastfca_init accepts (the
+ * resident and the wide kernel families). E_UNSUPPORTED for a FastMNMF
+ * context, whose updates are MM by construction.
  */
 int fastfca_set_algorithm(fastfca_ctx *c, int algo);
 

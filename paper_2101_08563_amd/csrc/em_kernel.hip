@@ -128,23 +128,23 @@ hipError_t launch_em_persistent(const EmLaunch &a, int threads, int bpt, int gri
 }
 
 // ------------------------------------------------------------------ wide family
-template <> void (*wide_lookup<2>(int, int, bool))(EmLaunch);
-template <> void (*wide_lookup<3>(int, int, bool))(EmLaunch);
-template <> void (*wide_lookup<4>(int, int, bool))(EmLaunch);
-template <> void (*wide_lookup<5>(int, int, bool))(EmLaunch);
-template <> void (*wide_lookup<6>(int, int, bool))(EmLaunch);
-template <> void (*wide_lookup<7>(int, int, bool))(EmLaunch);
-template <> void (*wide_lookup<8>(int, int, bool))(EmLaunch);
+template <> void (*wide_lookup<2>(int, int, bool, bool))(EmLaunch);
+template <> void (*wide_lookup<3>(int, int, bool, bool))(EmLaunch);
+template <> void (*wide_lookup<4>(int, int, bool, bool))(EmLaunch);
+template <> void (*wide_lookup<5>(int, int, bool, bool))(EmLaunch);
+template <> void (*wide_lookup<6>(int, int, bool, bool))(EmLaunch);
+template <> void (*wide_lookup<7>(int, int, bool, bool))(EmLaunch);
+template <> void (*wide_lookup<8>(int, int, bool, bool))(EmLaunch);
 
-static EmFn wide_fn(int M, int N, int bpt, bool prio = false) {
+static EmFn wide_fn(int M, int N, int bpt, bool prio = false, bool mm = false) {
     switch (M) {
-        case 2: return wide_lookup<2>(N, bpt, prio);
-        case 3: return wide_lookup<3>(N, bpt, prio);
-        case 4: return wide_lookup<4>(N, bpt, prio);
-        case 5: return wide_lookup<5>(N, bpt, prio);
-        case 6: return wide_lookup<6>(N, bpt, prio);
-        case 7: return wide_lookup<7>(N, bpt, prio);
-        case 8: return wide_lookup<8>(N, bpt, prio);
+        case 2: return wide_lookup<2>(N, bpt, prio, mm);
+        case 3: return wide_lookup<3>(N, bpt, prio, mm);
+        case 4: return wide_lookup<4>(N, bpt, prio, mm);
+        case 5: return wide_lookup<5>(N, bpt, prio, mm);
+        case 6: return wide_lookup<6>(N, bpt, prio, mm);
+        case 7: return wide_lookup<7>(N, bpt, prio, mm);
+        case 8: return wide_lookup<8>(N, bpt, prio, mm);
         default: return nullptr;
     }
 }
@@ -162,7 +162,7 @@ int em_wide_blocks_per_cu(int M, int N, int bpt, int threads) {
 
 hipError_t launch_em_wide(int M, int N, int bpt, int threads, const EmLaunch &a, int grid,
                           hipStream_t s) {
-    EmFn fn = wide_fn(M, N, bpt, a.prio != 0);
+    EmFn fn = wide_fn(M, N, bpt, a.prio != 0, a.algo == kAlgoMM);
     if (!fn) return hipErrorInvalidValue;
     if (threads < 64 || (threads & 63) || threads * bpt > kWideMaxT || threads > wide_max_threads(bpt))
         return hipErrorInvalidValue;

@@ -94,7 +94,9 @@ __device__ __forceinline__ void load_bins(gx_ptr x, int t, int T, float2 (&out)[
     }
 }
 
-template <int M, int N, int BPT>
+// MM: Algorithm 2's update of L and H in phase C instead of Algorithm 1's (a
+// separate instance, so that each update's register allocation is its own).
+template <int M, int N, int BPT, bool MM>
 __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, double alarm, int trace_off,
                                              WideSmem &sm) {
     constexpr int M2 = M * M;
@@ -293,7 +295,98 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, dou
         }
 
         asm volatile("" ::: "memory");  // phase boundary: no code motion across it (registers)
-        // ---------------- phase C: sources in order
+        if constexpr (MM) {
+            // ---------------- phase C (Algorithm 2): MM update of L from the
+            // current L and H, then of H with the new L. Per channel m, the
+            // wave's sums over its bins of U v / sigma^4 and v / sigma^2 for
+            // every source go to its stage region ([M][2N]); one thread per
+            // (n, m) adds the waves in order and writes the new l_nm (to
+            // qtot, idle until the next phase A); every wave copies it into
+            // its own L.
+            float *rmm = stg;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                float lc[N];
+#pragma unroll
+                for (int nn = 0; nn < N; ++nn) lc[nn] = lamw[nn * M + m];
+                float acc[2 * N];
+#pragma unroll
+                for (int i = 0; i < 2 * N; ++i) acc[i] = 0.0f;
+#pragma unroll
+                for (int k = 0; k < BPT; ++k) {
+                    float s = 0.0f;
+#pragma unroll
+                    for (int nn = 0; nn < N; ++nn) s = fmaf(vr[k][nn], lc[nn], s);
+                    const float is = ((vmask >> k) & 1u) ? rcp(s) : 0.0f;
+                    const float ua = U[k][m] * is * is;
+#pragma unroll
+                    for (int n = 0; n < N; ++n) {
+                        acc[n] = fmaf(ua, vr[k][n], acc[n]);
+                        acc[N + n] = fmaf(is, vr[k][n], acc[N + n]);
+                    }
+                }
+                constexpr int NG = (2 * N + 3) / 4;
+                float tot[NG];
+                wave_sums_rows<2 * N>(acc, tot);
+                if ((lane & 15) == 0) {
+#pragma unroll
+                    for (int g = 0; g < NG; ++g)
+                        if (4 * g + (lane >> 4) < 2 * N) rmm[m * 2 * N + 4 * g + (lane >> 4)] = tot[g];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            __syncthreads();
+            float *lnew = reinterpret_cast<float *>(sm.qtot);
+            for (int i = tid; i < N * M; i += nthr) {
+                const int n = i / M, m = i % M;
+                float num = 0.0f, den = 0.0f;
+                for (int w = 0; w < nw; ++w) {
+                    const float *p = sm.stage + w * region + m * 2 * N;
+                    num += p[n];
+                    den += p[N + n];
+                }
+                lnew[i] = lamw[i] * sqrtf(num / den);
+            }
+            __syncthreads();
+            bool good = true;
+            for (int i = lane; i < N * M; i += 64) {
+                const float l = lnew[i];
+                good = good && (l > 0.0f) && (l < INFINITY);
+                lamw[i] = l;
+            }
+            if (!__all(good)) {  // the same values in every wave
+                status = ST_NONFINITE;
+                break;
+            }
+            // H rule with the new L, local to each bin
+#pragma unroll
+            for (int k = 0; k < BPT; ++k) {
+                float num[N], den[N];
+#pragma unroll
+                for (int n = 0; n < N; ++n) num[n] = den[n] = 0.0f;
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    float lc[N];
+#pragma unroll
+                    for (int nn = 0; nn < N; ++nn) lc[nn] = lamw[nn * M + m];
+                    float s = 0.0f;
+#pragma unroll
+                    for (int nn = 0; nn < N; ++nn) s = fmaf(vr[k][nn], lc[nn], s);
+                    const float is = rcp(s);
+                    const float ua = U[k][m] * is * is;
+#pragma unroll
+                    for (int n = 0; n < N; ++n) {
+                        num[n] = fmaf(lc[n], ua, num[n]);
+                        den[n] = fmaf(lc[n], is, den[n]);
+                    }
+                }
+                const bool valid = (vmask >> k) & 1u;
+#pragma unroll
+                for (int n = 0; n < N; ++n) vr[k][n] = valid ? vr[k][n] * sqrtf(num[n] / den[n]) : 1.0f;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+        // ---------------- phase C (Algorithm 1): sources in order
 #pragma unroll 1
         for (int n = 0; n < N; ++n) {
             float *es = stg;  // [BPT][M][64], lane-contiguous
@@ -372,6 +465,7 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, dou
                     if (nn == n) vr[k][nn] = vnew;
             }
         }
+        }  // Algorithm 1
         if (status != ST_OK) break;
         // log-likelihood terms of the new iterate (eq:negll), reported in the
         // next pass of phase A

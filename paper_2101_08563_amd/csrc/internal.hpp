@@ -72,7 +72,7 @@ bool em_tail_supported(int M, int N, int bpt, bool cov = false);
 // global memory each iteration; see em_wide.hpp. One lookup per M, defined in
 // the per-M translation units of em_wide_kernel.hip.
 template <int M>
-void (*wide_lookup(int N, int bpt, bool prio))(EmLaunch);
+void (*wide_lookup(int N, int bpt, bool prio, bool mm))(EmLaunch);
 hipError_t launch_em_wide(int M, int N, int bpt, int threads, const EmLaunch &a, int grid,
                           hipStream_t s);
 bool em_wide_supported(int M, int N, int bpt);

@@ -1121,12 +1121,6 @@ int fastfca_set_algorithm(fastfca_ctx *c, int algo) {
     if (algo != FASTFCA_ALGO_EM && algo != FASTFCA_ALGO_MM)
         return set_err(c, FASTFCA_E_ARG, "unknown algorithm %d", algo);
     if (c->mn) return set_err(c, FASTFCA_E_UNSUPPORTED, "FastMNMF updates Lambda, T and V by MM only");
-    if (algo == FASTFCA_ALGO_MM)
-        for (const auto &cc : c->classes)
-            if (cc.wide)
-                return set_err(c, FASTFCA_E_UNSUPPORTED,
-                               "IP+MM is compiled for the resident family only (M<=4, N<=8, T<=2048); "
-                               "M=%d N=%d T=%d", cc.M, cc.N, cc.Tmax);
     c->algo = algo == FASTFCA_ALGO_MM ? kAlgoMM : kAlgoEM;
     drop_graph(c);
     return FASTFCA_OK;

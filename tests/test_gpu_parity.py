@@ -286,15 +286,6 @@ def test_ip_mm_algorithm2_parity(M, N, T, F):
     assert np.diff(trace).min() > -1e-5
 
 
-def test_ip_mm_rejected_for_wide_shapes():
-    x, P0, lam0, v0 = make_case(3, 300, 6, 7, config_id=99)
-    ctx = FastFCA(*to_dev(x), 7)
-    with pytest.raises(FastFCAError) as e:
-        ctx.set_algorithm("mm")
-    assert e.value.code == -7
-    ctx.close()
-
-
 def test_ll_alarm_reports_a_decrease():
     """The likelihood alarm, forced from the host: a tolerance of -10 asks
     for a gain of 10 nats per bin per iteration, so every frequency stops at

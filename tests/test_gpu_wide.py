@@ -18,12 +18,13 @@ def dev(*arrs):
     return [torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in arrs]
 
 
-def run(x, P0, lam0, v0, iters, config=None):
+def run(x, P0, lam0, v0, iters, config=None, algo="em"):
     N = lam0.shape[1]
     xd, Pd, ld, vd = dev(x, P0, lam0, v0)
     ctx = FastFCA(xd, N, Pd, ld, vd)
     if config:
         ctx.set_config(*config)
+    ctx.set_algorithm(algo)
     ctx.em_step(iters)
     ctx.sync()
     out = dict(trace=ctx.ll_trace(), ll=ctx.loglik(), cfg=ctx.get_config())
@@ -52,6 +53,27 @@ def test_wide_family_parity(M, N, T):
     # the trace's per-bin terms are single precision logarithms; with up to
     # eight channels per bin they stay within 2e-6 nats/bin (1.3e-6 observed)
     assert errs["ll"] < 1e-6 and errs["tr"] < 2e-6, errs
+
+
+@pytest.mark.parametrize("M,N,T", [(5, 6, 300), (8, 10, 777), (6, 2, 64), (7, 9, 2100)])
+def test_wide_family_mm_parity(M, N, T):
+    # Algorithm 2 (IP+MM) in the wide kernel against the oracle's MM rules
+    F, iters = 5, 12
+    x = synth.mixture(F=F, T=T, M=M, N=N, rank=3, diffuse=0.1, config_id=90 + M, mixture_id=N)
+    P0, lam0, v0 = synth.init_params(x, N, config_id=90 + M, mixture_id=N)
+    g = run(x, P0, lam0, v0, iters, algo="mm")
+    Po, lo, vo, tro = oracle.fit(x, P0, lam0, v0, iters, algo=1, trace=True)
+    llo, _ = oracle.loglik(x, Po, lo, vo)
+    yo = oracle.mwf(x, Po, lo, vo)
+    errs = report(g, Po, lo, vo, yo)
+    errs.update(ll=abs(g["ll"] - llo), tr=float(np.abs(g["trace"] - tro).max()))
+    print("wide mm", M, N, T, g["cfg"], {k: "%.2e" % e for k, e in errs.items()}, flush=True)
+    for k in ("v", "lam", "P", "y", "v_f", "lam_f", "P_f", "y_f"):
+        assert errs[k] < 1e-4, (k, errs)
+    assert errs["v_log999"] < 1e-3, errs
+    assert errs["ll"] < 1e-6 and errs["tr"] < 2e-6, errs
+    # Algorithm 2 never lowers the likelihood either
+    assert np.all(np.diff(g["trace"]) > -1e-6), g["trace"]
 
 
 def test_wide_launch_shapes_agree():
