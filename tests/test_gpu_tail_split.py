@@ -88,6 +88,15 @@ def test_split_wide_family_partial_last_round(blocks):
     _same(_run(p, 20, blocks), _run(p, 20, 0))
 
 
+def test_split_wide_family_with_algorithm_2():
+    """The wide family's Algorithm 2 instance and its tail instance."""
+    from paper_2101_08563_amd.fastfca import synth_mixture
+    F = _ncu() + 1
+    x = synth_mixture(F, 1500, 6, 7, rank=6, diffuse=0.05, seed=12)
+    p = [(x, 7)]
+    _same(_run(p, 16, -1, algo="mm"), _run(p, 16, 0, algo="mm"))
+
+
 def test_set_tail_split_rejects_bad_values():
     ctx = FastFCA(_mix(8, 64, 2, 2, 3), 2, seed=1)
     from paper_2101_08563_amd.fastfca import FastFCAError
