@@ -59,6 +59,7 @@ struct WideSmem {
     alignas(16) float red[2][kWideMaxM][kWideWaves];
     alignas(16) double red_d[kWideWaves];
     float lamw[kWideWaves][kWideMaxN * kWideMaxM];
+    float lam_new[kWideMaxN * kWideMaxM];  // Algorithm 2: the new L, formed once for every wave
     double qtot[kWideMaxM * kWideMaxM * kWideMaxM];
     double2 Pd[kWideMaxM * kWideMaxM];
     float2 P32[kWideMaxM * kWideMaxM];
@@ -300,9 +301,8 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, dou
             // current L and H, then of H with the new L. Per channel m, the
             // wave's sums over its bins of U v / sigma^4 and v / sigma^2 for
             // every source go to its stage region ([M][2N]); one thread per
-            // (n, m) adds the waves in order and writes the new l_nm (to
-            // qtot, idle until the next phase A); every wave copies it into
-            // its own L.
+            // (n, m) adds the waves in order and writes the new l_nm;
+            // every wave copies it into its own L.
             float *rmm = stg;
 #pragma unroll
             for (int m = 0; m < M; ++m) {
@@ -336,7 +336,7 @@ __device__ __forceinline__ void em_wide_item(const WorkItem &it, int n_iter, dou
                 __builtin_amdgcn_sched_barrier(0);
             }
             __syncthreads();
-            float *lnew = reinterpret_cast<float *>(sm.qtot);
+            float *lnew = sm.lam_new;
             for (int i = tid; i < N * M; i += nthr) {
                 const int n = i / M, m = i % M;
                 float num = 0.0f, den = 0.0f;
