@@ -239,10 +239,20 @@ int threads_for(int T, int bpt, int cap = kResidentBins) {
 
 bool pick_default(int M, int Tmax, int &threads, int &bpt) {
     // Four bins per thread; eight for M = 2, 3 beyond 1024 frames. Measured on
-    // gfx950 with 513 frequencies: two bins per thread was never the fastest;
+    // gfx950 with 513 frequencies: beyond 256 frames two bins per thread was
+    // never the fastest;
     // beyond 1024 frames eight bins per thread (half the wavefronts) ran 25 %
     // (M = 2) to 30 % (M = 3) faster than four; for M = 4 four stayed ahead.
+    // For M = 2 and at most 256 frames (or blocks), where four bins per
+    // thread leave one wavefront per workgroup, two bins per thread (two
+    // wavefronts) ran 3-4 % faster (513 frequencies, T = 250 and 256).
     const bool long2 = (M == 2 || M == 3) && Tmax > 1024;
+    const bool short2 = M == 2 && threads_for(Tmax, 4) == 64 && threads_for(Tmax, 2) == 128;
+    if (short2) {
+        threads = 128;
+        bpt = 2;
+        return true;
+    }
     for (int b : {long2 ? 8 : 4, long2 ? 4 : 8, 2}) {
         const int th = threads_for(Tmax, b);
         if (th) {
