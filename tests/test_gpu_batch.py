@@ -144,6 +144,23 @@ def test_single_autotune_cache(tmp_path):
     ctx.close()
 
 
+@pytest.mark.parametrize("M,T,cfg", [(2, 250, (128, 2)), (2, 256, (128, 2)), (2, 128, (64, 4)),
+                                     (2, 1000, (256, 4)), (2, 2000, (256, 8)), (3, 250, (64, 4)),
+                                     (4, 1000, (256, 4))])
+def test_default_launch_shapes(M, T, cfg):
+    """The default (threads, bins per thread) of a single mixture: two bins
+    per thread for M = 2 at 129-256 frames (two wavefronts), eight beyond
+    1024 frames for M = 2, 3, four otherwise; and the fit under it matches the oracle."""
+    x = synth.mixture(F=3, T=T, M=M, N=M + 1, config_id=41)
+    P0, lam0, v0 = synth.init_params(x, M + 1, config_id=41)
+    ctx = FastFCA(torch.from_numpy(x).to(DEV), M + 1, *(torch.from_numpy(a).to(DEV) for a in (P0, lam0, v0)))
+    assert tuple(ctx.get_config()) == cfg
+    ctx.em_step(5)
+    Po, lo, vo, _ = oracle.fit(x, P0, lam0, v0, 5)
+    assert rel(ctx.get_params()[2].cpu().numpy(), vo) < 1e-4
+    ctx.close()
+
+
 def test_batch_with_a_wide_class_uses_class_launches():
     """A batch holding a mixture outside the persistent kernel's classes (M = 5:
     the wide family) runs with the class schedule; the persistent schedule is
