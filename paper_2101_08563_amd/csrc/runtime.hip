@@ -237,23 +237,29 @@ int threads_for(int T, int bpt, int cap = kResidentBins) {
     return th * bpt <= cap ? th : 0;
 }
 
-bool pick_default(int M, int Tmax, int &threads, int &bpt) {
-    // Four bins per thread; eight for M = 2, 3 beyond 1024 frames. Measured on
-    // gfx950 with 513 frequencies: beyond 256 frames two bins per thread was
-    // never the fastest;
-    // beyond 1024 frames eight bins per thread (half the wavefronts) ran 25 %
-    // (M = 2) to 30 % (M = 3) faster than four; for M = 4 four stayed ahead.
-    // For M = 2 and at most 256 frames (or blocks), where four bins per
-    // thread leave one wavefront per workgroup, two bins per thread (two
-    // wavefronts) ran 3-4 % faster (513 frequencies, T = 250 and 256).
-    const bool long2 = (M == 2 || M == 3) && Tmax > 1024;
-    const bool short2 = M == 2 && threads_for(Tmax, 4) == 64 && threads_for(Tmax, 2) == 128;
-    if (short2) {
+// Default (threads, bins per thread) of a class; M = 0: the persistent
+// kernel's shape for a batch (four bins per thread first).
+bool pick_default(int M, int N, int Tmax, int &threads, int &bpt) {
+    // From sweeps on gfx950 over M = 2, 3, 4, N = M + 1 .. 8 and T = 200..2000
+    // (513 frequencies, 100 iterations, every shape that fits):
+    //   T <= 256:        four (at M = 2 from 129 frames two, in two
+    //                    wavefronts: 3-4 % faster on the 250-block
+    //                    piecewise model);
+    //   256 < T <= 512:  eight, one wavefront (up to 6 % faster than four,
+    //                    ties at N = 8), except M = 3, N = 5, whose
+    //                    eight-bin instance spills (3.5 % slower);
+    //   512 < T <= 1024: four;
+    //   T > 1024:        eight (M = 2, 3: 25-30 % faster than four; M = 4:
+    //                    1-4 %).
+    // Two bins per thread was never the fastest beyond 256 frames.
+    if (M == 2 && threads_for(Tmax, 4) == 64 && threads_for(Tmax, 2) == 128) {
         threads = 128;
         bpt = 2;
         return true;
     }
-    for (int b : {long2 ? 8 : 4, long2 ? 4 : 8, 2}) {
+    const bool mid = threads_for(Tmax, 4) == 128 && !(M == 3 && N == 5);
+    const bool eight = M > 0 && (Tmax > 1024 || mid);
+    for (int b : {eight ? 8 : 4, eight ? 4 : 8, 2}) {
         const int th = threads_for(Tmax, b);
         if (th) {
             threads = th;
@@ -274,10 +280,10 @@ bool use_resident(int M, int N, int Tmax) {
 bool pick_class(ClassCfg &cc) {
     if (cc.cov) {  // block model: resident family only
         cc.wide = false;
-        return use_resident(cc.M, cc.N, cc.Tmax) && pick_default(cc.M, cc.Tmax, cc.threads, cc.bpt);
+        return use_resident(cc.M, cc.N, cc.Tmax) && pick_default(cc.M, cc.N, cc.Tmax, cc.threads, cc.bpt);
     }
     cc.wide = !use_resident(cc.M, cc.N, cc.Tmax);
-    if (!cc.wide) return pick_default(cc.M, cc.Tmax, cc.threads, cc.bpt);
+    if (!cc.wide) return pick_default(cc.M, cc.N, cc.Tmax, cc.threads, cc.bpt);
     cc.bpt = 8;
     cc.threads = threads_for(cc.Tmax, 8, kWideMaxT);  // at most 512 (kWideMaxThreads)
     return cc.threads != 0 && em_wide_supported(cc.M, cc.N, 8);
@@ -544,7 +550,7 @@ int create(fastfca_ctx **out, int B, const fastfca_problem *probs, uint64_t seed
                 Tmax = std::max(Tmax, cc.Tmax);
                 ok = ok && !cc.wide && persistent_supported(cc.M, cc.N);
             }
-            if (!ok || !pick_default(0, Tmax, c->p_threads, c->p_bpt)) {
+            if (!ok || !pick_default(0, 0, Tmax, c->p_threads, c->p_bpt)) {
                 c->persistent = false;
                 c->p_threads = 0;
             }

@@ -144,16 +144,18 @@ def test_single_autotune_cache(tmp_path):
     ctx.close()
 
 
-@pytest.mark.parametrize("M,T,cfg", [(2, 250, (128, 2)), (2, 256, (128, 2)), (2, 128, (64, 4)),
-                                     (2, 1000, (256, 4)), (2, 2000, (256, 8)), (3, 250, (64, 4)),
-                                     (4, 1000, (256, 4))])
-def test_default_launch_shapes(M, T, cfg):
+@pytest.mark.parametrize("M,N,T,cfg", [(2, 3, 250, (128, 2)), (2, 3, 256, (128, 2)), (2, 3, 128, (64, 4)),
+                                       (2, 3, 400, (64, 8)), (2, 3, 1000, (256, 4)), (2, 3, 2000, (256, 8)),
+                                       (3, 4, 250, (64, 4)), (3, 4, 400, (64, 8)), (3, 5, 400, (128, 4)),
+                                       (4, 5, 1000, (256, 4)), (4, 6, 1500, (192, 8))])
+def test_default_launch_shapes(M, N, T, cfg):
     """The default (threads, bins per thread) of a single mixture: two bins
-    per thread for M = 2 at 129-256 frames (two wavefronts), eight beyond
-    1024 frames for M = 2, 3, four otherwise; and the fit under it matches the oracle."""
-    x = synth.mixture(F=3, T=T, M=M, N=M + 1, config_id=41)
-    P0, lam0, v0 = synth.init_params(x, M + 1, config_id=41)
-    ctx = FastFCA(torch.from_numpy(x).to(DEV), M + 1, *(torch.from_numpy(a).to(DEV) for a in (P0, lam0, v0)))
+    per thread for M = 2 at 129-256 frames (two wavefronts); eight at
+    257-512 frames (one wavefront; not for M = 3, N = 5) and beyond 1024
+    frames; four otherwise; and the fit under it matches the oracle."""
+    x = synth.mixture(F=3, T=T, M=M, N=N, config_id=41)
+    P0, lam0, v0 = synth.init_params(x, N, config_id=41)
+    ctx = FastFCA(torch.from_numpy(x).to(DEV), N, *(torch.from_numpy(a).to(DEV) for a in (P0, lam0, v0)))
     assert tuple(ctx.get_config()) == cfg
     ctx.em_step(5)
     Po, lo, vo, _ = oracle.fit(x, P0, lam0, v0, 5)
