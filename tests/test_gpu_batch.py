@@ -147,12 +147,14 @@ def test_single_autotune_cache(tmp_path):
 @pytest.mark.parametrize("M,N,T,cfg", [(2, 3, 250, (128, 2)), (2, 3, 256, (128, 2)), (2, 3, 128, (64, 4)),
                                        (2, 3, 400, (64, 8)), (2, 3, 1000, (256, 4)), (2, 3, 2000, (256, 8)),
                                        (3, 4, 250, (64, 4)), (3, 4, 400, (64, 8)), (3, 5, 400, (128, 4)),
-                                       (4, 5, 1000, (256, 4)), (4, 6, 1500, (192, 8))])
+                                       (4, 5, 1000, (256, 4)), (4, 6, 1500, (192, 8)),
+                                       (6, 7, 1000, (256, 4)), (6, 7, 3000, (384, 8))])
 def test_default_launch_shapes(M, N, T, cfg):
     """The default (threads, bins per thread) of a single mixture: two bins
     per thread for M = 2 at 129-256 frames (two wavefronts); eight at
     257-512 frames (one wavefront; not for M = 3, N = 5) and beyond 1024
-    frames; four otherwise; and the fit under it matches the oracle."""
+    frames; four otherwise; the wide family (M = 6) four up to 2048 frames,
+    eight beyond; and the fit under it matches the oracle."""
     x = synth.mixture(F=3, T=T, M=M, N=N, config_id=41)
     P0, lam0, v0 = synth.init_params(x, N, config_id=41)
     ctx = FastFCA(torch.from_numpy(x).to(DEV), N, *(torch.from_numpy(a).to(DEV) for a in (P0, lam0, v0)))
