@@ -9,8 +9,8 @@
 
 namespace ffca {
 
-// PRIO: the tail instance of the tail split (see em_kernel.hip), at eight
-// bins per thread only. MM: Algorithm 2 (IP+MM) instead of Algorithm 1.
+// PRIO: the tail instance of the tail split (see em_kernel.hip). MM:
+// Algorithm 2 (IP+MM) instead of Algorithm 1.
 template <int M, int N, int BPT, bool PRIO, bool MM>
 __global__ void __launch_bounds__(wide_max_threads(BPT)) em_wide_kernel(EmLaunch a) {
     static_assert(wide_max_threads(BPT) / 64 <= kWideWaves, "reduction slots per wave");
@@ -27,7 +27,7 @@ using WideFn = void (*)(EmLaunch);
 template <int M, int N, bool MM>
 static WideFn wide_bpt_algo(int bpt, bool prio) {
     switch (bpt) {
-        case 4: return prio ? nullptr : em_wide_kernel<M, N, 4, false, MM>;
+        case 4: return prio ? em_wide_kernel<M, N, 4, true, MM> : em_wide_kernel<M, N, 4, false, MM>;
         case 8: return prio ? em_wide_kernel<M, N, 8, true, MM> : em_wide_kernel<M, N, 8, false, MM>;
         default: return nullptr;
     }

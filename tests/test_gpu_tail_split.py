@@ -88,6 +88,17 @@ def test_split_wide_family_partial_last_round(blocks):
     _same(_run(p, 20, blocks), _run(p, 20, 0))
 
 
+def test_split_wide_family_four_bins_per_thread():
+    """The wide family at four bins per thread (up to 2048 frames) and its
+    tail instance."""
+    from paper_2101_08563_amd.fastfca import synth_mixture
+    F = _ncu() + 1
+    x = synth_mixture(F, 1500, 6, 7, rank=6, diffuse=0.05, seed=13)
+    p = [(x, 7)]
+    _same(_run(p, 16, -1), _run(p, 16, 0))
+    _same(_run(p, 16, -1, algo="mm"), _run(p, 16, 0, algo="mm"))
+
+
 def test_split_wide_family_with_algorithm_2():
     """The wide family's Algorithm 2 instance and its tail instance (beyond
     2048 frames, where the wide family takes eight bins per thread)."""
